@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs for the TVB-AdEx sweep path.
+
+This module is the ONLY code shared by the GPU library's callers and the CPU
+oracle's tests. It draws random numbers and lays out parameter grids; it holds
+none of the method's arithmetic (no weight normalisation, no delays, no model
+equations).
+
+Stand-ins: the paper's 68-region human connectome (Section 2.4, the ``-cf``
+flag) is not available, so a synthetic connectome with the same region count
+and the same role (symmetric weights, tract lengths in mm) replaces it. The
+sweep axes follow Section 2.3 (one parameter combination per instance, grids of
+equally spaced values per axis) and the parameter ranges of Table 4.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+
+import numpy as np
+
+# Region counts of the three size classes and the generator seed of each.
+CONNECTOME_SEEDS = {68: 0, 84: 1, 200: 2}
+
+# Box of the swept parameters (S, b_e [pA], a_e [nS], v [m/s]).
+SWEEP_BOX = {"S": (0.0, 0.5), "b_e": (0.0, 120.0), "a_e": (0.0, 8.0), "v": (1.0, 10.0)}
+
+
+@dataclasses.dataclass
+class Connectome:
+    """Raw structural connectivity of one synthetic brain.
+
+    weights: [n, n] float64, symmetric, zero diagonal, raw (not normalised).
+    tract_mm: [n, n] float64, symmetric, zero diagonal, lengths in mm.
+    """
+
+    weights: np.ndarray
+    tract_mm: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.weights.shape[0])
+
+
+def synthetic_connectome(n: int = 68, seed: int | None = None, density: float = 0.2,
+                         lognorm_mu: float = -2.0, lognorm_sigma: float = 1.0,
+                         len_lo: float = 10.0, len_hi: float = 200.0) -> Connectome:
+    """Symmetric random connectome: each pair i<j is an edge with probability
+    ``density``; edge weights are LogNormal(mu, sigma); tract lengths are
+    U(len_lo, len_hi) mm for every pair. Draw order is fixed: edge mask, then
+    weights, then lengths, each as a full [n, n] draw whose upper triangle is
+    mirrored."""
+    if seed is None:
+        seed = CONNECTOME_SEEDS.get(n, n)
+    rng = np.random.default_rng(seed)
+    mask = rng.random((n, n)) < density
+    w = rng.lognormal(lognorm_mu, lognorm_sigma, (n, n))
+    L = rng.uniform(len_lo, len_hi, (n, n))
+    iu = np.triu_indices(n, 1)
+    W = np.zeros((n, n))
+    W[iu] = np.where(mask[iu], w[iu], 0.0)
+    W = W + W.T
+    T = np.zeros((n, n))
+    T[iu] = L[iu]
+    T = T + T.T
+    return Connectome(weights=W, tract_mm=T)
+
+
+@dataclasses.dataclass
+class Batch:
+    """One parameter combination per instance, FP32 as the library takes them."""
+
+    S: np.ndarray
+    b_e: np.ndarray
+    a_e: np.ndarray
+    v: np.ndarray
+    conn: np.ndarray  # int32 connectome index per instance
+
+    def __len__(self) -> int:
+        return int(self.S.shape[0])
+
+    def subset(self, idx) -> "Batch":
+        idx = np.asarray(idx)
+        return Batch(self.S[idx], self.b_e[idx], self.a_e[idx], self.v[idx], self.conn[idx])
+
+
+def _batch(S, b_e, a_e, v, conn=None) -> Batch:
+    S = np.asarray(S, np.float32)
+    n = S.shape[0]
+    conn = np.zeros(n, np.int32) if conn is None else np.asarray(conn, np.int32)
+    return Batch(S, np.asarray(b_e, np.float32), np.asarray(a_e, np.float32),
+                 np.asarray(v, np.float32), conn)
+
+
+def grid_small() -> Batch:
+    """8 combos: S in {0.1, 0.3} x b_e in {0, 60} x a_e in {0, 4}, v = 4 m/s
+    (S outermost, a_e innermost)."""
+    rows = list(itertools.product([0.1, 0.3], [0.0, 60.0], [0.0, 4.0]))
+    S, b, a = (np.array(c) for c in zip(*rows))
+    return _batch(S, b, a, np.full(len(rows), 4.0))
+
+
+def grid_uniform(n_s: int = 64, n_b: int = 64, v: float = 4.0) -> Batch:
+    """n_s x n_b inclusive linspace over S in [0, 0.5] x b_e in [0, 120] with
+    a_e = 0 and one conduction speed (S outermost)."""
+    S = np.linspace(*SWEEP_BOX["S"], n_s)
+    b = np.linspace(*SWEEP_BOX["b_e"], n_b)
+    SS, BB = np.meshgrid(S, b, indexing="ij")
+    n = SS.size
+    return _batch(SS.ravel(), BB.ravel(), np.zeros(n), np.full(n, v))
+
+
+def grid_uneven(n_inst: int = 8192, seed: int = 3, sizes=(68, 84, 200)) -> Batch:
+    """Mixed batch: region-count classes in equal thirds (shuffled), v ~ U(1, 10),
+    S, b_e, a_e uniform over the sweep box. ``conn`` indexes ``sizes``."""
+    rng = np.random.default_rng(seed)
+    k = len(sizes)
+    cls = np.repeat(np.arange(k), -(-n_inst // k))[:n_inst]
+    rng.shuffle(cls)
+    u = rng.random((n_inst, 4))
+    lo = np.array([SWEEP_BOX[a][0] for a in ("S", "b_e", "a_e", "v")])
+    hi = np.array([SWEEP_BOX[a][1] for a in ("S", "b_e", "a_e", "v")])
+    p = lo + u * (hi - lo)
+    return _batch(p[:, 0], p[:, 1], p[:, 2], p[:, 3], cls)
+
+
+def sample_box(n: int = 32768, seed: int = 4) -> Batch:
+    """Uniform random points in the 4-D sweep box (surrogate training set)."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n, 4))
+    lo = np.array([SWEEP_BOX[a][0] for a in ("S", "b_e", "a_e", "v")])
+    hi = np.array([SWEEP_BOX[a][1] for a in ("S", "b_e", "a_e", "v")])
+    p = lo + u * (hi - lo)
+    return _batch(p[:, 0], p[:, 1], p[:, 2], p[:, 3])
+
+
+def grid_4d(res: int = 32) -> Batch:
+    """res^4 inclusive linspace grid over the sweep box (S outermost, v innermost)."""
+    axes = [np.linspace(*SWEEP_BOX[a], res) for a in ("S", "b_e", "a_e", "v")]
+    G = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 4)
+    return _batch(G[:, 0], G[:, 1], G[:, 2], G[:, 3])
+
+
+@dataclasses.dataclass
+class RunConfig:
+    """Time axis of one sweep run. Steps of dt ms; a rate sample is the mean of
+    ``tavg_steps`` consecutive steps; samples starting before
+    ``transient_steps`` are dropped from the FC."""
+
+    dt_ms: float = 0.1
+    n_steps: int = 10000
+    transient_steps: int = 0
+    tavg_steps: int = 10
+    seed: int = 0
+    n_trace_steps: int = 0
+
+    @property
+    def n_samples(self) -> int:
+        return (self.n_steps - self.transient_steps) // self.tavg_steps
+
+
+# Named workloads: (batch factory, region classes, run config).
+RUN_SMALL = RunConfig(n_steps=10000, transient_steps=0)           # 1 s, no transient
+RUN_UNIFORM = RunConfig(n_steps=100000, transient_steps=10000)    # 10 s, 1 s transient
+RUN_UNEVEN = RunConfig(n_steps=50000, transient_steps=10000)      # 5 s, 1 s transient
