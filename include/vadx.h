@@ -1,0 +1,183 @@
+/*
+ * vadx.h -- C ABI of the MI355X TVB-AdEx sweep engine.
+ *
+ * The engine integrates many independent whole-brain networks at once, one
+ * parameter combination per network ("instance"), as in the parameter sweeps
+ * of van der Vlag et al., "Vast TVB parameter space exploration"
+ * (arXiv:2311.13337), Section 2.3: each instance is a connectome of regions,
+ * each region steps the second-order AdEx mean field of Section 2.1
+ * (eq. 1-3: rates E, I, covariances C_ee, C_ei, C_ii, adaptation W_e, W_i)
+ * plus Ornstein-Uhlenbeck noise (eq. 4), driven through the transfer function
+ * of Section 2.2 (template + Table 1 threshold polynomial) by the delayed,
+ * weighted excitatory rates of the other regions (eq. 5). After the run the
+ * Pearson functional connectivity of the time-averaged rates (Section 2.4,
+ * eq. 6) and summary statistics are formed per instance.
+ *
+ * Conventions
+ *  - Every call returns a vadx_status; nothing throws across this boundary and
+ *    nothing aborts. vadx_last_error() describes the last failure on a context.
+ *  - Host arrays passed in are copied before the call returns (caller keeps
+ *    ownership). Device pointers (workspace, outputs with where=VADX_DEVICE)
+ *    are borrowed: the caller owns them and keeps them alive until the work
+ *    that uses them has completed (vadx_sync).
+ *  - Work is enqueued on the stream given to vadx_create (stream-ordered);
+ *    reads with where=VADX_HOST synchronise that stream.
+ *  - A context belongs to one device and one stream and is not thread-safe.
+ *  - Results are a pure function of (model, connectome, parameters, run, seed,
+ *    instance index): they do not depend on launch shapes or batch order.
+ *  - Units: time in ms, rates in kHz inside the model (statistics report Hz),
+ *    voltages in mV, conductances in nS, currents in pA, capacitance in pF,
+ *    tract lengths in mm, conduction speeds in m/s (= mm/ms).
+ */
+#ifndef VADX_H
+#define VADX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vadx_status;
+enum {
+    VADX_OK = 0,
+    VADX_E_ARG = -1,         /* invalid argument (sizes, NaN/negative parameters, bad connectome) */
+    VADX_E_OOM = -2,         /* workspace too small or a device allocation failed */
+    VADX_E_HIP = -3,         /* a HIP runtime call failed */
+    VADX_E_STATE = -4,       /* call out of order (e.g. integrate before set_batch) */
+    VADX_E_NUMERIC = -5,     /* reserved */
+    VADX_E_UNSUPPORTED = -6  /* request outside what the build supports (e.g. too many regions) */
+};
+enum { VADX_HOST = 0, VADX_DEVICE = 1 };
+enum { VADX_PRESET_LITERATURE_B = 0, VADX_PRESET_PAPER_T1 = 1 };
+enum { VADX_HEUN = 0, VADX_EULER = 1 };
+/* per-instance flag bits in vadx_stats.flags */
+enum { VADX_FLAG_NONFINITE = 1u, VADX_FLAG_CLAMP = 2u, VADX_FLAG_ZERO_VAR = 4u };
+
+typedef struct vadx_ctx vadx_ctx;
+
+/* Model constants shared by all instances (Section 2.1-2.2). P_e / P_i are
+ * the ten threshold-polynomial coefficients of Table 1 (mV) in the table's
+ * column order for the excitatory (RS) and inhibitory (FS) cell.
+ * K_e, K_i: number of excitatory / inhibitory synapses per neuron (the
+ * weights of the excitatory and inhibitory input rates). N_e, N_i: population
+ * sizes in the finite-size term of eq. (2). cF_mn: constant drive to the
+ * n-input of population m's transfer function (eq. 5). sigma_OU, w_noise: the
+ * OU amplitude of eq. (4) and its weight on the excitatory input. x_floor:
+ * minimum input rate of the transfer function. rate_max: upper clamp of E, I. */
+typedef struct vadx_model {
+    double C_m, g_L, E_e, E_i, Q_e, Q_i, tau_e, tau_i, K_e, K_i, N_e, N_i, T;
+    double E_L_e, E_L_i, tau_w_e, tau_w_i, b_i, a_i;
+    double cF_ee, cF_ei, cF_ie, cF_ii;
+    double tau_OU, sigma_OU, w_noise;
+    double muV0, dmuV0, sV0, dsV0, tN0, dtN0;
+    double rate_max, E_init, I_init, x_floor;
+    double P_e[10], P_i[10];
+} vadx_model;
+
+/* One run over the current batch. Samples are means of tavg_steps steps; the
+ * first transient_steps are left out of the FC and statistics. seed keys the
+ * Philox noise together with the instance index. n_trace_steps > 0 records the
+ * full state after each of the first n_trace_steps steps for the instances
+ * chosen with vadx_set_trace. noise_off = 1 runs the noise-free system. */
+typedef struct vadx_run {
+    double dt_ms;
+    int64_t n_steps, transient_steps, tavg_steps, n_trace_steps;
+    uint32_t seed;
+    int32_t integrator;   /* VADX_HEUN (default) or VADX_EULER */
+    int32_t noise_off;
+    int32_t chunk_steps;  /* steps per kernel launch; 0 = library default */
+} vadx_run;
+
+/* Summary statistics of one instance (definitions in vadx_read_stats). */
+typedef struct vadx_stats {
+    float fc_mean, fc_std, fc_sc_corr, rate_mean_hz, rate_std_hz, sync_index;
+    uint32_t flags, reserved;
+} vadx_stats;
+
+/* Creates a context on HIP device `device` enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). The stream is borrowed. */
+vadx_status vadx_create(int device, void *hip_stream, vadx_ctx **out);
+void vadx_destroy(vadx_ctx *ctx);
+/* Text of the last error on ctx (valid until the next call on ctx); never NULL. */
+const char *vadx_last_error(const vadx_ctx *ctx);
+
+/* Fills *out with a preset: VADX_PRESET_PAPER_T1 uses Table 1 as printed;
+ * VADX_PRESET_LITERATURE_B reads three entries of Table 1 as misprints
+ * (RS P0 = -49.8, FS P_muV = 4.0, both P_sigmaVtauN with opposite sign). */
+vadx_status vadx_model_defaults(int preset, vadx_model *out);
+/* Sets the model for subsequent runs (copied). */
+vadx_status vadx_set_model(vadx_ctx *ctx, const vadx_model *model);
+
+/* Registers a connectome of n regions (Section 2.4, "-cf"): raw weights w
+ * [n*n] row-major (non-negative, zero diagonal) and tract lengths [n*n] in mm
+ * (positive where w > 0). Weights are row-normalised on the device
+ * (W_kj = w_kj / sum_j w_kj; all-zero rows stay zero); the raw w is the
+ * structural connectivity used for the FC-SC correlation. 2 <= n <= 1024.
+ * *conn_id receives the index used by vadx_set_batch. */
+vadx_status vadx_add_connectome(vadx_ctx *ctx, int32_t n, const double *weights,
+                                const double *tract_mm, int32_t *conn_id);
+
+/* Sets the batch: one parameter combination per instance (Section 2.3) --
+ * global coupling S >= 0, spike-frequency adaptation b_e (pA), subthreshold
+ * adaptation a_e (nS), conduction speed v > 0 (m/s) -- and the connectome of
+ * each instance (NULL = all 0). Host arrays of n_inst entries, copied. */
+vadx_status vadx_set_batch(vadx_ctx *ctx, int64_t n_inst, const float *S, const float *b_e,
+                           const float *a_e, const float *v_mps, const int32_t *conn_id);
+
+/* Chooses up to 1024 instances whose first run->n_trace_steps states are
+ * recorded (trace slot i = inst[i]). n = 0 clears the selection. */
+vadx_status vadx_set_trace(vadx_ctx *ctx, int64_t n, const int64_t *inst);
+
+/* Bytes of device workspace vadx_integrate needs for `run` on the current
+ * batch: state, delay rings, rate samples, traces, FC and statistics. */
+vadx_status vadx_plan(vadx_ctx *ctx, const vadx_run *run, size_t *workspace_bytes);
+
+/* Integrates every instance of the batch for run->n_steps steps of
+ * stochastic Heun (or Euler), then forms the FC and the statistics.
+ * workspace: device memory of at least the planned size, 256-byte aligned,
+ * owned by the caller; results live there until the next integrate. */
+vadx_status vadx_integrate(vadx_ctx *ctx, const vadx_run *run, void *workspace,
+                           size_t workspace_bytes);
+
+/* Waits for all work of ctx. */
+vadx_status vadx_sync(vadx_ctx *ctx);
+
+/* Reads results of the last vadx_integrate. `out` is host (VADX_HOST) or
+ * device (VADX_DEVICE) memory owned by the caller.
+ *  vadx_read_stats: `count` vadx_stats from instance `first`. fc_mean/fc_std:
+ *    mean and population std of FC_kl over k<l; fc_sc_corr: Pearson
+ *    correlation of FC_kl with the raw weights w_kl over k<l; rate_mean_hz:
+ *    mean of E over regions and samples; rate_std_hz: mean over regions of
+ *    the temporal std of E; sync_index: sqrt(var_t(mean_k E_k) /
+ *    mean_k var_t(E_k)). flags: VADX_FLAG_* bits.
+ *  vadx_read_fc: the n x n FC matrix (float) of instance `inst`.
+ *  vadx_read_samples: the [n_samples][n] rate samples (kHz) of `inst`.
+ *  vadx_read_state: the final [8][n] state of `inst` (E, I, C_ee, C_ei, C_ii,
+ *    W_e, W_i, OU).
+ *  vadx_read_trace: [n_trace_steps][8][n] states of trace slot `slot`. */
+vadx_status vadx_read_stats(vadx_ctx *ctx, int64_t first, int64_t count, vadx_stats *out,
+                            int32_t where);
+vadx_status vadx_read_fc(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
+vadx_status vadx_read_samples(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
+vadx_status vadx_read_state(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
+vadx_status vadx_read_trace(vadx_ctx *ctx, int64_t slot, float *out, int32_t where);
+
+/* Region count and number of post-transient samples of instance `inst` for
+ * the last plan (sizes of the read_* outputs). */
+vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,
+                                int64_t *n_samples);
+
+/* Kernel timing: when enabled, HIP events on the context's stream bracket every
+ * launch of the integration kernel; vadx_kernel_time reports their count and
+ * summed duration (ms) since the last reset, and the duration of the FC
+ * kernel launches. */
+vadx_status vadx_enable_timing(vadx_ctx *ctx, int32_t on);
+vadx_status vadx_kernel_time(vadx_ctx *ctx, int64_t *n_integrate_launches, double *integrate_ms,
+                             int64_t *n_fc_launches, double *fc_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VADX_H */

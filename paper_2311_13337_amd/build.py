@@ -1,0 +1,60 @@
+"""Builds libvadx.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
+
+Packed FP32 instructions are switched off for all device code
+(-target-feature -packed-fp32-ops); the host pass warns that it does not know
+the feature, which is harmless.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libvadx.so")
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "vadx_api.cpp")]
+ARCH = os.environ.get("VADX_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    h = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(h):
+        raise RuntimeError("hipcc not found")
+    return h
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every source and links libvadx.so (always rebuilds)."""
+    objs = []
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    for src in SOURCES:
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = [hipcc(), *common, "-c", src, "-o", obj]
+        if src.endswith(".cpp"):
+            cmd = [hipcc(), *common, "-x", "hip", "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc failed on {src}")
+        if verbose:
+            sys.stderr.write(r.stderr)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    r = subprocess.run([hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link of libvadx.so failed")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

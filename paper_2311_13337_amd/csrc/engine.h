@@ -1,0 +1,94 @@
+// engine.h -- device data layout and kernel launchers of the sweep engine
+// (internal to libvadx; the public boundary is include/vadx.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adex_model.h"
+
+namespace vadx {
+
+// Largest number of steps integrated between two workgroup barriers. A block
+// of B steps reads the delay rings before writing any of its own rates, which
+// is exact as long as B <= d_min + 1 (the shortest delay plus one).
+constexpr int kMaxBlock = 16;
+
+// One instance = one parameter combination on one connectome.
+struct InstDev {
+    float S, be, ae;
+    int32_t n;          // regions
+    int32_t D;          // ring depth in steps (slots per region row)
+    int32_t conn;       // connectome
+    uint32_t id;        // instance index (Philox key word 1)
+    int32_t pad;
+    int64_t table_off;  // into the packed delay tables (nnz entries)
+    int64_t trace_off;  // floats: [n_trace][8][n]; -1: not traced
+    int64_t state_off;  // floats: [8][n] final/resume state
+    int64_t acc_off;    // floats: [n] running time-average sums
+    int64_t ring_off;   // floats: [n][D] excitatory-rate history
+    int64_t samp_off;   // floats: [n_samples][n]
+    int64_t fc_off;     // floats: [n][n]
+};
+
+// Connectome in CSR form (ascending column order inside each row).
+struct ConnDev {
+    int32_t n, nnz;
+    int64_t row_off;    // into rowptr (n + 1 entries)
+    int64_t edge_off;   // into colw / len arrays (nnz entries)
+    int64_t sc_off;     // into raw weights (n*n doubles)
+};
+
+// A workgroup's share: `count` instances of the same region count.
+struct GroupDev {
+    int32_t first;      // into the instance permutation
+    int32_t count;
+    int32_t n;
+    int32_t pad;
+};
+
+struct DelayTableDev {
+    int32_t conn;
+    float v;            // conduction speed (m/s)
+    int64_t off;        // into packed edges: (column << 20) | delay
+};
+
+struct IntegrateArgs {
+    KModel M;
+    const InstDev *inst;
+    const int32_t *perm;
+    const GroupDev *groups;
+    const ConnDev *conns;
+    const int32_t *rowptr;
+    const float *weight;        // row-normalised weights per CSR edge
+    const int32_t *packed;      // per delay table and edge: (column << 20) | delay
+    float *ws;                  // workspace base (floats)
+    uint32_t *flags;            // per instance
+    int64_t n_steps_total, transient_steps, tavg_steps, n_trace_steps, n_samples;
+    int64_t n_begin, n_end;
+    float dt, gdw_scale;        // gdw_scale = sigma_OU / tau_OU * sqrt(dt) (0: noise off)
+    uint32_t seed;
+    int32_t integrator;
+    int32_t block;              // steps per barrier block (<= kMaxBlock)
+};
+
+struct FcArgs {
+    const InstDev *inst;
+    const ConnDev *conns;
+    const double *sc;           // raw weights, [n][n] per connectome
+    float *ws;
+    float *stats;               // [inst][8] as vadx_stats (6 floats + flags + reserved)
+    uint32_t *flags;
+    int64_t n_samples;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_conn_prepare(int n, const double *w, const double *len, int32_t *rowptr,
+                               float *weight, double *edge_len, int32_t *colidx, hipStream_t s);
+hipError_t launch_delays(int n_tables, const DelayTableDev *tables, const ConnDev *conns,
+                         const int32_t *colidx, const double *edge_len, double dt,
+                         int32_t *packed, int max_nnz, hipStream_t s);
+hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
+                            hipStream_t s);
+hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s);
+
+} // namespace vadx

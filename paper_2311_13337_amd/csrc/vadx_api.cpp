@@ -1,0 +1,713 @@
+// vadx_api.cpp -- host side of the C ABI declared in include/vadx.h: argument
+// checks, model conversion, connectome and batch bookkeeping, the workspace
+// planner (instance grouping, ring depths, delay tables) and the launch
+// sequence of one run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "engine.h"
+#include "vadx.h"
+
+using namespace vadx;
+
+namespace {
+
+struct HostConn {
+    int32_t n = 0, nnz = 0;
+    double len_min = 0.0, len_max = 0.0;   // over edges with w != 0
+    int64_t row_off = 0, edge_off = 0, sc_off = 0;
+};
+
+template <class T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t count)
+    {
+        if (count <= n && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+} // namespace
+
+struct vadx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    vadx_model model{};
+    bool have_model = false;
+    // connectomes (device copies grow as connectomes are added)
+    std::vector<HostConn> conns;
+    std::vector<int32_t> h_rowptr_sizes;
+    int64_t total_rows = 0, total_edges = 0, total_sc = 0;
+    DevBuf<int32_t> rowptr, colidx;
+    DevBuf<float> weight;
+    DevBuf<double> edge_len, sc;
+    DevBuf<ConnDev> d_conns;
+    // batch
+    std::vector<float> S, be, ae, v;
+    std::vector<int32_t> conn_of;
+    std::vector<int64_t> traced;
+    // plan
+    bool planned = false;
+    vadx_run plan_run{};
+    int block = 1;
+    int wg_threads = 64;
+    std::vector<InstDev> h_inst;
+    std::vector<int32_t> h_perm;
+    std::vector<GroupDev> h_groups;
+    std::vector<DelayTableDev> h_tables;
+    int max_nnz = 0;
+    int64_t packed_total = 0;
+    int64_t n_samples = 0;
+    size_t ws_bytes = 0;
+    size_t off_stats = 0, off_flags = 0;
+    DevBuf<InstDev> d_inst;
+    DevBuf<int32_t> d_perm;
+    DevBuf<GroupDev> d_groups;
+    DevBuf<DelayTableDev> d_tables;
+    DevBuf<int32_t> d_packed;
+    // last run
+    void *ws = nullptr;
+    bool ran = false;
+    // timing
+    bool timing = false;
+    int64_t n_int = 0, n_fc = 0;
+    double ms_int = 0.0, ms_fc = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_int, ev_fc;
+    int max_groups_per_launch = 0;   // 0: all groups
+    int wg_instances_override = 0;
+};
+
+static vadx_status fail(vadx_ctx *c, vadx_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIP_TRY(c, expr)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((c), e_ == hipErrorOutOfMemory ? VADX_E_OOM : VADX_E_HIP, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                                \
+    } while (0)
+
+static const double kRS[10] = {-48.9, 5.1, -25.0, 1.4, -0.41, 10.5, -36.0, 7.4, 1.2, 40.7};
+static const double kFS[10] = {-51.4, 0.4, -8.3, 0.2, -0.5, 1.4, -14.6, 4.5, 2.8, 15.3};
+
+extern "C" {
+
+vadx_status vadx_model_defaults(int preset, vadx_model *m)
+{
+    if (!m || (preset != VADX_PRESET_LITERATURE_B && preset != VADX_PRESET_PAPER_T1))
+        return VADX_E_ARG;
+    std::memset(m, 0, sizeof(*m));
+    m->C_m = 200.0; m->g_L = 10.0; m->E_e = 0.0; m->E_i = -80.0;
+    m->Q_e = 1.5; m->Q_i = 5.0; m->tau_e = 5.0; m->tau_i = 5.0;
+    m->K_e = 400.0; m->K_i = 100.0; m->N_e = 8000.0; m->N_i = 2000.0; m->T = 20.0;
+    m->E_L_e = -64.0; m->E_L_i = -65.0; m->tau_w_e = 500.0; m->tau_w_i = 1.0;
+    m->b_i = 0.0; m->a_i = 0.0;
+    m->cF_ee = 0.3e-3; m->cF_ei = 0.0; m->cF_ie = 0.3e-3; m->cF_ii = 0.0;
+    m->tau_OU = 5.0; m->sigma_OU = 1e-3; m->w_noise = 1e-3;
+    m->muV0 = -60.0; m->dmuV0 = 10.0; m->sV0 = 4.0; m->dsV0 = 6.0; m->tN0 = 0.5; m->dtN0 = 1.0;
+    m->rate_max = 1.0; m->E_init = 0.01; m->I_init = 0.01; m->x_floor = 1e-6;
+    std::memcpy(m->P_e, kRS, sizeof(kRS));
+    std::memcpy(m->P_i, kFS, sizeof(kFS));
+    if (preset == VADX_PRESET_LITERATURE_B) {
+        m->P_e[0] = -49.8;
+        m->P_i[1] = 4.0;
+        m->P_e[9] = -m->P_e[9];
+        m->P_i[9] = -m->P_i[9];
+    }
+    return VADX_OK;
+}
+
+vadx_status vadx_create(int device, void *hip_stream, vadx_ctx **out)
+{
+    if (!out) return VADX_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return VADX_E_HIP;
+    if (device < 0 || device >= ndev) return VADX_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return VADX_E_HIP;
+    vadx_ctx *c = new vadx_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    vadx_model_defaults(VADX_PRESET_LITERATURE_B, &c->model);
+    c->have_model = true;
+    *out = c;
+    return VADX_OK;
+}
+
+void vadx_destroy(vadx_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &e : c->ev_int) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto &e : c->ev_fc) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    c->rowptr.release(); c->colidx.release(); c->weight.release(); c->edge_len.release();
+    c->sc.release(); c->d_conns.release(); c->d_inst.release(); c->d_perm.release();
+    c->d_groups.release(); c->d_tables.release(); c->d_packed.release();
+    delete c;
+}
+
+const char *vadx_last_error(const vadx_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+static bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+vadx_status vadx_set_model(vadx_ctx *c, const vadx_model *m)
+{
+    if (!c || !m) return fail(c, VADX_E_ARG, "null argument");
+    const double pos[] = {m->C_m, m->g_L, m->Q_e, m->Q_i, m->tau_e, m->tau_i, m->K_e, m->K_i,
+                          m->N_e, m->N_i, m->T, m->tau_w_e, m->tau_w_i, m->tau_OU, m->dmuV0,
+                          m->dsV0, m->dtN0, m->rate_max};
+    for (double x : pos)
+        if (!(std::isfinite(x) && x > 0.0)) return fail(c, VADX_E_ARG, "model constant must be > 0");
+    const double any[] = {m->E_e, m->E_i, m->E_L_e, m->E_L_i, m->b_i, m->a_i, m->cF_ee, m->cF_ei,
+                          m->cF_ie, m->cF_ii, m->sigma_OU, m->w_noise, m->muV0, m->sV0, m->tN0,
+                          m->E_init, m->I_init, m->x_floor};
+    for (double x : any)
+        if (!std::isfinite(x)) return fail(c, VADX_E_ARG, "model constant not finite");
+    for (int i = 0; i < 10; ++i)
+        if (!std::isfinite(m->P_e[i]) || !std::isfinite(m->P_i[i]))
+            return fail(c, VADX_E_ARG, "threshold coefficient not finite");
+    if (!(m->x_floor > 0.0)) return fail(c, VADX_E_ARG, "x_floor must be > 0");
+    if (m->E_init < 0 || m->E_init > m->rate_max || m->I_init < 0 || m->I_init > m->rate_max)
+        return fail(c, VADX_E_ARG, "initial rates outside [0, rate_max]");
+    c->model = *m;
+    c->have_model = true;
+    return VADX_OK;
+}
+
+vadx_status vadx_add_connectome(vadx_ctx *c, int32_t n, const double *w, const double *len,
+                                int32_t *conn_id)
+{
+    if (!c || !w || !len || !conn_id) return fail(c, VADX_E_ARG, "null argument");
+    if (n < 2) return fail(c, VADX_E_ARG, "need at least 2 regions");
+    if (n > 1024) return fail(c, VADX_E_UNSUPPORTED, "at most 1024 regions per connectome");
+    HostConn hc;
+    hc.n = n;
+    int64_t nnz = 0;
+    double lmin = INFINITY, lmax = 0.0;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j) {
+            const double x = w[(int64_t)k * n + j], L = len[(int64_t)k * n + j];
+            if (!finite_nonneg(x)) return fail(c, VADX_E_ARG, "weights must be finite and >= 0");
+            if (!std::isfinite(L) || L < 0.0) return fail(c, VADX_E_ARG, "tract lengths must be finite and >= 0");
+            if (x != 0.0) {
+                if (k == j) return fail(c, VADX_E_ARG, "self-connection w[%d][%d] != 0", k, k);
+                if (!(L > 0.0)) return fail(c, VADX_E_ARG, "edge %d-%d has no positive length", k, j);
+                ++nnz;
+                lmin = std::min(lmin, L);
+                lmax = std::max(lmax, L);
+            }
+        }
+    hc.nnz = (int32_t)nnz;
+    hc.len_min = nnz ? lmin : 0.0;
+    hc.len_max = lmax;
+    hc.row_off = c->total_rows;
+    hc.edge_off = c->total_edges;
+    hc.sc_off = c->total_sc;
+    HIP_TRY(c, hipSetDevice(c->device));
+    // grow device arrays, keeping earlier connectomes
+    auto grow = [&](auto &buf, size_t need) -> hipError_t {
+        using T = std::remove_pointer_t<decltype(buf.p)>;
+        if (need <= buf.n) return hipSuccess;
+        T *np = nullptr;
+        hipError_t e = hipMalloc((void **)&np, need * sizeof(T) * 2);
+        if (e != hipSuccess) return e;
+        if (buf.p) {
+            e = hipMemcpyAsync(np, buf.p, buf.n * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            (void)hipFree(buf.p);
+            if (e != hipSuccess) { (void)hipFree(np); buf.p = nullptr; buf.n = 0; return e; }
+        }
+        buf.p = np;
+        buf.n = need * 2;
+        return hipSuccess;
+    };
+    HIP_TRY(c, grow(c->rowptr, (size_t)(c->total_rows + n + 1)));
+    HIP_TRY(c, grow(c->colidx, (size_t)(c->total_edges + nnz + 1)));
+    HIP_TRY(c, grow(c->weight, (size_t)(c->total_edges + nnz + 1)));
+    HIP_TRY(c, grow(c->edge_len, (size_t)(c->total_edges + nnz + 1)));
+    HIP_TRY(c, grow(c->sc, (size_t)(c->total_sc + (int64_t)n * n)));
+    double *dlen = nullptr;
+    HIP_TRY(c, hipMalloc((void **)&dlen, sizeof(double) * n * n));
+    hipError_t e = hipMemcpyAsync(c->sc.p + hc.sc_off, w, sizeof(double) * n * n,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dlen, len, sizeof(double) * n * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_conn_prepare(n, c->sc.p + hc.sc_off, dlen, c->rowptr.p + hc.row_off,
+                                c->weight.p + hc.edge_off, c->edge_len.p + hc.edge_off,
+                                c->colidx.p + hc.edge_off, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dlen);
+    if (e != hipSuccess) return fail(c, VADX_E_HIP, "connectome upload: %s", hipGetErrorString(e));
+    c->total_rows += n + 1;
+    c->total_edges += nnz;
+    c->total_sc += (int64_t)n * n;
+    c->conns.push_back(hc);
+    std::vector<ConnDev> dc;
+    for (auto &h : c->conns) dc.push_back(ConnDev{h.n, h.nnz, h.row_off, h.edge_off, h.sc_off});
+    HIP_TRY(c, c->d_conns.ensure(dc.size()));
+    HIP_TRY(c, hipMemcpyAsync(c->d_conns.p, dc.data(), dc.size() * sizeof(ConnDev),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *conn_id = (int32_t)c->conns.size() - 1;
+    c->planned = false;
+    return VADX_OK;
+}
+
+vadx_status vadx_set_batch(vadx_ctx *c, int64_t n, const float *S, const float *b_e,
+                           const float *a_e, const float *v, const int32_t *conn)
+{
+    if (!c) return VADX_E_ARG;
+    if (n < 0 || (n > 0 && (!S || !b_e || !a_e || !v))) return fail(c, VADX_E_ARG, "bad batch arrays");
+    if (n > (int64_t)1 << 31) return fail(c, VADX_E_UNSUPPORTED, "batch too large");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!finite_nonneg(S[i])) return fail(c, VADX_E_ARG, "S[%lld] must be finite and >= 0", (long long)i);
+        if (!std::isfinite(b_e[i]) || !std::isfinite(a_e[i]))
+            return fail(c, VADX_E_ARG, "b_e/a_e[%lld] not finite", (long long)i);
+        if (!(std::isfinite(v[i]) && v[i] > 0.0f))
+            return fail(c, VADX_E_ARG, "v[%lld] must be finite and > 0", (long long)i);
+        const int32_t ci = conn ? conn[i] : 0;
+        if (ci < 0 || ci >= (int32_t)c->conns.size())
+            return fail(c, VADX_E_ARG, "conn_id[%lld] = %d unknown", (long long)i, ci);
+    }
+    c->S.assign(S, S + n);
+    c->be.assign(b_e, b_e + n);
+    c->ae.assign(a_e, a_e + n);
+    c->v.assign(v, v + n);
+    c->conn_of.assign((size_t)n, 0);
+    if (conn) c->conn_of.assign(conn, conn + n);
+    c->traced.clear();
+    c->planned = false;
+    c->ran = false;
+    return VADX_OK;
+}
+
+vadx_status vadx_set_trace(vadx_ctx *c, int64_t n, const int64_t *inst)
+{
+    if (!c || n < 0 || n > 1024 || (n > 0 && !inst)) return fail(c, VADX_E_ARG, "bad trace selection");
+    for (int64_t i = 0; i < n; ++i)
+        if (inst[i] < 0 || inst[i] >= (int64_t)c->S.size())
+            return fail(c, VADX_E_ARG, "trace instance %lld out of range", (long long)inst[i]);
+    c->traced.assign(inst, inst + n);
+    c->planned = false;
+    return VADX_OK;
+}
+
+static bool run_ok(vadx_ctx *c, const vadx_run *r)
+{
+    if (!r) return false;
+    if (!(std::isfinite(r->dt_ms) && r->dt_ms > 0.0)) return false;
+    if (r->n_steps < 0 || r->transient_steps < 0 || r->tavg_steps <= 0 || r->n_trace_steps < 0)
+        return false;
+    if (r->transient_steps > r->n_steps) return false;
+    if (r->integrator != VADX_HEUN && r->integrator != VADX_EULER) return false;
+    if (r->chunk_steps < 0) return false;
+    (void)c;
+    return true;
+}
+
+// Delay in steps as the delays kernel computes it (FP64, round half to even).
+static int64_t host_delay(double L, float v, double dt)
+{
+    double q = std::nearbyint(L / ((double)v * dt));
+    return q < 1.0 ? 1 : (int64_t)q;
+}
+
+vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
+{
+    if (!c || !bytes) return fail(c, VADX_E_ARG, "null argument");
+    if (!run_ok(c, r)) return fail(c, VADX_E_ARG, "invalid run settings");
+    const int64_t ni = (int64_t)c->S.size();
+    if (ni == 0) return fail(c, VADX_E_STATE, "no batch set");
+    const int64_t ns = (r->n_steps - r->transient_steps) / r->tavg_steps;
+    // ring depths and the block length: a block of B steps reads histories up
+    // to B-1 steps ahead of its first step, so B <= d_min + 1; rings hold
+    // d_max + B + 1 slots so a block's writes never overwrite a value that a
+    // lane of the same block still has to read.
+    int64_t dmin_all = INT64_MAX;
+    std::vector<int64_t> dmax(ni);
+    for (int64_t i = 0; i < ni; ++i) {
+        const HostConn &hc = c->conns[c->conn_of[i]];
+        const int64_t dm = hc.nnz ? host_delay(hc.len_min, c->v[i], r->dt_ms) : 1;
+        dmax[i] = hc.nnz ? host_delay(hc.len_max, c->v[i], r->dt_ms) : 1;
+        dmin_all = std::min(dmin_all, dm);
+        if (dmax[i] >= (1 << 20) - kMaxBlock - 2)
+            return fail(c, VADX_E_UNSUPPORTED, "delay of %lld steps too long", (long long)dmax[i]);
+    }
+    int B = 1;
+    while (B * 2 <= kMaxBlock && B * 2 <= dmin_all + 1) B *= 2;
+    c->block = B;
+    // delay tables: one per distinct (connectome, speed)
+    std::map<std::pair<int32_t, uint32_t>, int32_t> tab;
+    c->h_tables.clear();
+    std::vector<int32_t> tab_of(ni);
+    int64_t poff = 0;
+    c->max_nnz = 0;
+    for (int64_t i = 0; i < ni; ++i) {
+        uint32_t vb;
+        std::memcpy(&vb, &c->v[i], 4);
+        auto key = std::make_pair(c->conn_of[i], vb);
+        auto it = tab.find(key);
+        if (it == tab.end()) {
+            const HostConn &hc = c->conns[c->conn_of[i]];
+            DelayTableDev t{c->conn_of[i], c->v[i], poff};
+            poff += hc.nnz;
+            c->max_nnz = std::max(c->max_nnz, hc.nnz);
+            it = tab.emplace(key, (int32_t)c->h_tables.size()).first;
+            c->h_tables.push_back(t);
+        }
+        tab_of[i] = it->second;
+    }
+    c->packed_total = poff;
+    // groups: instances of one connectome, ordered by ring depth, up to
+    // `per` instances (and 512 lanes) per workgroup
+    std::vector<int32_t> order(ni);
+    for (int64_t i = 0; i < ni; ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (c->conn_of[a] != c->conn_of[b]) return c->conn_of[a] < c->conn_of[b];
+        return dmax[a] < dmax[b];
+    });
+    c->h_groups.clear();
+    c->h_perm = order;
+    int max_threads = 64;
+    for (int64_t s = 0; s < ni;) {
+        const int32_t cid = c->conn_of[order[s]];
+        const int n = c->conns[cid].n;
+        int per = std::max(1, 512 / n);
+        if (c->wg_instances_override > 0) per = std::min(per, c->wg_instances_override);
+        int64_t e = s;
+        while (e < ni && e - s < per && c->conn_of[order[e]] == cid) ++e;
+        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, 0});
+        max_threads = std::max(max_threads, (int)(((e - s) * n + 63) / 64 * 64));
+        s = e;
+    }
+    c->wg_threads = max_threads;
+    // workspace layout (floats unless noted), each section 256-byte aligned
+    c->h_inst.assign(ni, InstDev{});
+    int64_t f_state = 0, f_acc = 0, f_ring = 0, f_samp = 0, f_fc = 0, f_trace = 0;
+    for (int64_t i = 0; i < ni; ++i) {
+        const HostConn &hc = c->conns[c->conn_of[i]];
+        InstDev &d = c->h_inst[i];
+        d.S = c->S[i]; d.be = c->be[i]; d.ae = c->ae[i];
+        d.n = hc.n;
+        d.D = (int32_t)(dmax[i] + B + 1);
+        d.conn = c->conn_of[i];
+        d.id = (uint32_t)i;
+        d.table_off = c->h_tables[tab_of[i]].off;
+        d.trace_off = -1;
+        d.state_off = f_state; f_state += 8LL * hc.n;
+        d.acc_off = f_acc; f_acc += hc.n;
+        d.ring_off = f_ring; f_ring += (int64_t)hc.n * d.D;
+        d.samp_off = f_samp; f_samp += (ns > 0 ? ns : 0) * hc.n;
+        d.fc_off = f_fc; f_fc += (int64_t)hc.n * hc.n;
+    }
+    if (r->n_trace_steps > 0)
+        for (int64_t t : c->traced) {
+            InstDev &d = c->h_inst[t];
+            d.trace_off = f_trace;
+            f_trace += r->n_trace_steps * 8 * d.n;
+        }
+    size_t off = 0;
+    auto section = [&](int64_t floats) { size_t o = off; off = align_up(off + floats * 4, 256); return o; };
+    const size_t o_state = section(f_state), o_acc = section(f_acc), o_ring = section(f_ring);
+    const size_t o_samp = section(f_samp), o_fc = section(f_fc), o_trace = section(f_trace);
+    c->off_stats = off; off = align_up(off + (size_t)ni * sizeof(vadx_stats), 256);
+    c->off_flags = off; off = align_up(off + (size_t)ni * 4, 256);
+    for (auto &d : c->h_inst) {
+        d.state_off += o_state / 4; d.acc_off += o_acc / 4; d.ring_off += o_ring / 4;
+        d.samp_off += o_samp / 4; d.fc_off += o_fc / 4;
+        if (d.trace_off >= 0) d.trace_off += o_trace / 4;
+    }
+    c->n_samples = ns > 0 ? ns : 0;
+    c->ws_bytes = off;
+    // device metadata
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, c->d_inst.ensure(ni));
+    HIP_TRY(c, c->d_perm.ensure(ni));
+    HIP_TRY(c, c->d_groups.ensure(c->h_groups.size()));
+    HIP_TRY(c, c->d_tables.ensure(c->h_tables.size()));
+    HIP_TRY(c, c->d_packed.ensure((size_t)std::max<int64_t>(c->packed_total, 1)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_inst.p, c->h_inst.data(), ni * sizeof(InstDev), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_perm.p, c->h_perm.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_groups.p, c->h_groups.data(), c->h_groups.size() * sizeof(GroupDev), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_tables.p, c->h_tables.data(), c->h_tables.size() * sizeof(DelayTableDev), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_delays((int)c->h_tables.size(), c->d_tables.p, c->d_conns.p, c->colidx.p,
+                             c->edge_len.p, r->dt_ms, c->d_packed.p, c->max_nnz, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->plan_run = *r;
+    c->planned = true;
+    c->ran = false;
+    *bytes = c->ws_bytes;
+    return VADX_OK;
+}
+
+static KModel make_kmodel(const vadx_model &m, double dt)
+{
+    (void)dt;
+    KModel k{};
+    k.aE = (float)(m.Q_e * m.tau_e * m.K_e);
+    k.aI = (float)(m.Q_i * m.tau_i * m.K_i);
+    k.gL = (float)m.g_L; k.Cm = (float)m.C_m; k.Ee = (float)m.E_e; k.Ei = (float)m.E_i;
+    k.Qe = (float)m.Q_e; k.Qi = (float)m.Q_i; k.tau_e = (float)m.tau_e; k.tau_i = (float)m.tau_i;
+    k.KeTe2 = (float)(m.K_e * m.tau_e * m.tau_e);
+    k.KiTi2 = (float)(m.K_i * m.tau_i * m.tau_i);
+    k.EL[0] = (float)m.E_L_e; k.EL[1] = (float)m.E_L_i;
+    k.gLEL[0] = (float)(m.g_L * m.E_L_e); k.gLEL[1] = (float)(m.g_L * m.E_L_i);
+    for (int i = 0; i < 10; ++i) { k.P[0][i] = (float)m.P_e[i]; k.P[1][i] = (float)m.P_i[i]; }
+    k.mu_s = (float)(1.0 / m.dmuV0); k.mu_o = (float)(-m.muV0 / m.dmuV0);
+    k.sg_s = (float)(1.0 / (std::sqrt(2.0) * m.dsV0)); k.sg_o = (float)(-m.sV0 / m.dsV0);
+    k.tn_s = (float)(m.g_L / (m.C_m * m.dtN0)); k.tn_o = (float)(-m.tN0 / m.dtN0);
+    k.invT = (float)(1.0 / m.T); k.invNe = (float)(1.0 / m.N_e); k.invNi = (float)(1.0 / m.N_i);
+    k.inv_tauw[0] = (float)(1.0 / m.tau_w_e); k.inv_tauw[1] = (float)(1.0 / m.tau_w_i);
+    k.b_i = (float)m.b_i; k.a_i = (float)m.a_i;
+    k.cF[0][0] = (float)m.cF_ee; k.cF[0][1] = (float)m.cF_ei;
+    k.cF[1][0] = (float)m.cF_ie; k.cF[1][1] = (float)m.cF_ii;
+    k.inv_tauOU = (float)(1.0 / m.tau_OU);
+    k.ou_gain = (float)(m.sigma_OU / m.tau_OU);
+    k.w_noise = (float)m.w_noise; k.rate_max = (float)m.rate_max; k.x_floor = (float)m.x_floor;
+    k.E_init = (float)m.E_init; k.I_init = (float)m.I_init;
+    return k;
+}
+
+static vadx_status record(vadx_ctx *c, std::vector<std::pair<hipEvent_t, hipEvent_t>> &evs,
+                          hipEvent_t *start)
+{
+    hipEvent_t a, b;
+    HIP_TRY(c, hipEventCreate(&a));
+    HIP_TRY(c, hipEventCreate(&b));
+    evs.emplace_back(a, b);
+    HIP_TRY(c, hipEventRecord(a, c->stream));
+    *start = b;
+    return VADX_OK;
+}
+
+vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_bytes)
+{
+    if (!c) return VADX_E_ARG;
+    if (!run_ok(c, r)) return fail(c, VADX_E_ARG, "invalid run settings");
+    if (!c->planned || std::memcmp(&c->plan_run, r, sizeof(vadx_run)) != 0)
+        return fail(c, VADX_E_STATE, "run differs from the last vadx_plan (call vadx_plan first)");
+    if (!ws || ((uintptr_t)ws & 255u)) return fail(c, VADX_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < c->ws_bytes)
+        return fail(c, VADX_E_OOM, "workspace of %zu bytes < planned %zu", ws_bytes, c->ws_bytes);
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t ni = (int64_t)c->S.size();
+    uint32_t *flags = (uint32_t *)((char *)ws + c->off_flags);
+    HIP_TRY(c, hipMemsetAsync(flags, 0, (size_t)ni * 4, c->stream));
+    IntegrateArgs a{};
+    a.M = make_kmodel(c->model, r->dt_ms);
+    a.inst = c->d_inst.p;
+    a.perm = c->d_perm.p;
+    a.groups = c->d_groups.p;
+    a.conns = c->d_conns.p;
+    a.rowptr = c->rowptr.p;
+    a.weight = c->weight.p;
+    a.packed = c->d_packed.p;
+    a.ws = (float *)ws;
+    a.flags = flags;
+    a.n_steps_total = r->n_steps;
+    a.transient_steps = r->transient_steps;
+    a.tavg_steps = r->tavg_steps;
+    a.n_trace_steps = r->n_trace_steps;
+    a.n_samples = c->n_samples;
+    a.dt = (float)r->dt_ms;
+    a.gdw_scale = r->noise_off ? 0.0f : (float)(c->model.sigma_OU / c->model.tau_OU * std::sqrt(r->dt_ms));
+    a.seed = r->seed;
+    a.integrator = r->integrator;
+    a.block = c->block;
+    int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps : 10000;
+    chunk = std::max<int64_t>(chunk / c->block, 1) * c->block;
+    const int ng = (int)c->h_groups.size();
+    for (int64_t n0 = 0; n0 < r->n_steps; n0 += chunk) {
+        a.n_begin = n0;
+        a.n_end = std::min<int64_t>(r->n_steps, n0 + chunk);
+        hipEvent_t stop = nullptr;
+        if (c->timing) { vadx_status st = record(c, c->ev_int, &stop); if (st) return st; }
+        HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, c->stream));
+        if (c->timing) HIP_TRY(c, hipEventRecord(stop, c->stream));
+    }
+    if (r->n_steps == 0) {
+        // nothing integrated: state is the initial state, no samples
+    }
+    FcArgs f{};
+    f.inst = c->d_inst.p;
+    f.conns = c->d_conns.p;
+    f.sc = c->sc.p;
+    f.ws = (float *)ws;
+    f.stats = (float *)((char *)ws + c->off_stats);
+    f.flags = flags;
+    f.n_samples = c->n_samples;
+    hipEvent_t stop = nullptr;
+    if (c->timing) { vadx_status st = record(c, c->ev_fc, &stop); if (st) return st; }
+    HIP_TRY(c, launch_fc_stats(f, ni, c->stream));
+    if (c->timing) HIP_TRY(c, hipEventRecord(stop, c->stream));
+    c->ws = ws;
+    c->ran = true;
+    return VADX_OK;
+}
+
+vadx_status vadx_sync(vadx_ctx *c)
+{
+    if (!c) return VADX_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return VADX_OK;
+}
+
+static vadx_status copy_out(vadx_ctx *c, void *dst, const void *src, size_t bytes, int32_t where)
+{
+    if (where != VADX_HOST && where != VADX_DEVICE) return fail(c, VADX_E_ARG, "bad `where`");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes,
+                              where == VADX_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                              c->stream));
+    if (where == VADX_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return VADX_OK;
+}
+
+static vadx_status check_read(vadx_ctx *c, int64_t inst, void *out)
+{
+    if (!c->ran) return fail(c, VADX_E_STATE, "no results: call vadx_integrate first");
+    if (!out) return fail(c, VADX_E_ARG, "null output");
+    if (inst < 0 || inst >= (int64_t)c->h_inst.size()) return fail(c, VADX_E_ARG, "instance out of range");
+    return VADX_OK;
+}
+
+vadx_status vadx_read_stats(vadx_ctx *c, int64_t first, int64_t count, vadx_stats *out, int32_t where)
+{
+    if (!c) return VADX_E_ARG;
+    if (count == 0) return VADX_OK;
+    vadx_status st = check_read(c, first, out);
+    if (st) return st;
+    if (count < 0 || first + count > (int64_t)c->h_inst.size()) return fail(c, VADX_E_ARG, "range out of bounds");
+    return copy_out(c, out, (char *)c->ws + c->off_stats + first * sizeof(vadx_stats),
+                    count * sizeof(vadx_stats), where);
+}
+
+vadx_status vadx_read_fc(vadx_ctx *c, int64_t inst, float *out, int32_t where)
+{
+    if (!c) return VADX_E_ARG;
+    vadx_status st = check_read(c, inst, out);
+    if (st) return st;
+    const InstDev &d = c->h_inst[inst];
+    return copy_out(c, out, (float *)c->ws + d.fc_off, sizeof(float) * d.n * d.n, where);
+}
+
+vadx_status vadx_read_samples(vadx_ctx *c, int64_t inst, float *out, int32_t where)
+{
+    if (!c) return VADX_E_ARG;
+    vadx_status st = check_read(c, inst, out);
+    if (st) return st;
+    const InstDev &d = c->h_inst[inst];
+    if (c->n_samples == 0) return VADX_OK;
+    return copy_out(c, out, (float *)c->ws + d.samp_off, sizeof(float) * d.n * c->n_samples, where);
+}
+
+vadx_status vadx_read_state(vadx_ctx *c, int64_t inst, float *out, int32_t where)
+{
+    if (!c) return VADX_E_ARG;
+    vadx_status st = check_read(c, inst, out);
+    if (st) return st;
+    const InstDev &d = c->h_inst[inst];
+    if (c->plan_run.n_steps == 0) return fail(c, VADX_E_STATE, "no steps were integrated");
+    return copy_out(c, out, (float *)c->ws + d.state_off, sizeof(float) * 8 * d.n, where);
+}
+
+vadx_status vadx_read_trace(vadx_ctx *c, int64_t slot, float *out, int32_t where)
+{
+    if (!c) return VADX_E_ARG;
+    if (slot < 0 || slot >= (int64_t)c->traced.size()) return fail(c, VADX_E_ARG, "trace slot out of range");
+    vadx_status st = check_read(c, c->traced[slot], out);
+    if (st) return st;
+    const InstDev &d = c->h_inst[c->traced[slot]];
+    if (d.trace_off < 0) return fail(c, VADX_E_STATE, "no trace recorded");
+    return copy_out(c, out, (float *)c->ws + d.trace_off,
+                    sizeof(float) * 8 * d.n * c->plan_run.n_trace_steps, where);
+}
+
+vadx_status vadx_instance_shape(vadx_ctx *c, int64_t inst, int32_t *n_regions, int64_t *n_samples)
+{
+    if (!c || !n_regions || !n_samples) return fail(c, VADX_E_ARG, "null argument");
+    if (!c->planned) return fail(c, VADX_E_STATE, "no plan");
+    if (inst < 0 || inst >= (int64_t)c->h_inst.size()) return fail(c, VADX_E_ARG, "instance out of range");
+    *n_regions = c->h_inst[inst].n;
+    *n_samples = c->n_samples;
+    return VADX_OK;
+}
+
+vadx_status vadx_enable_timing(vadx_ctx *c, int32_t on)
+{
+    if (!c) return VADX_E_ARG;
+    c->timing = on != 0;
+    return VADX_OK;
+}
+
+static vadx_status drain(vadx_ctx *c, std::vector<std::pair<hipEvent_t, hipEvent_t>> &evs,
+                         int64_t &n, double &ms)
+{
+    for (auto &e : evs) {
+        float t = 0.f;
+        HIP_TRY(c, hipEventSynchronize(e.second));
+        HIP_TRY(c, hipEventElapsedTime(&t, e.first, e.second));
+        ms += t;
+        ++n;
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    evs.clear();
+    return VADX_OK;
+}
+
+vadx_status vadx_kernel_time(vadx_ctx *c, int64_t *n_int, double *ms_int, int64_t *n_fc, double *ms_fc)
+{
+    if (!c || !n_int || !ms_int || !n_fc || !ms_fc) return fail(c, VADX_E_ARG, "null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    vadx_status st = drain(c, c->ev_int, c->n_int, c->ms_int);
+    if (st) return st;
+    st = drain(c, c->ev_fc, c->n_fc, c->ms_fc);
+    if (st) return st;
+    *n_int = c->n_int; *ms_int = c->ms_int; *n_fc = c->n_fc; *ms_fc = c->ms_fc;
+    c->n_int = c->n_fc = 0;
+    c->ms_int = c->ms_fc = 0.0;
+    return VADX_OK;
+}
+
+} // extern "C"

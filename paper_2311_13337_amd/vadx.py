@@ -1,0 +1,277 @@
+"""ctypes binding of libvadx (include/vadx.h): the same entry points, argument
+marshalling only. Device memory (the workspace) and the stream come from
+PyTorch; every step of the computation runs in the library's HIP kernels.
+
+Loading fails loudly when the library has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvadx.so")
+
+VADX_OK, VADX_E_ARG, VADX_E_OOM, VADX_E_HIP, VADX_E_STATE, VADX_E_NUMERIC, VADX_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+VADX_HOST, VADX_DEVICE = 0, 1
+VADX_PRESET_LITERATURE_B, VADX_PRESET_PAPER_T1 = 0, 1
+VADX_HEUN, VADX_EULER = 0, 1
+PRESETS = {"literature-B": VADX_PRESET_LITERATURE_B, "paper-T1": VADX_PRESET_PAPER_T1}
+STAT_NAMES = ("fc_mean", "fc_std", "fc_sc_corr", "rate_mean_hz", "rate_std_hz", "sync_index")
+
+EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_defaults",
+           "vadx_set_model", "vadx_add_connectome", "vadx_set_batch", "vadx_set_trace",
+           "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
+           "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
+           "vadx_enable_timing", "vadx_kernel_time")
+
+
+class VadxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"vadx status {status}: {msg}")
+        self.status = status
+
+
+class vadx_model(C.Structure):
+    _fields_ = [(f, C.c_double) for f in (
+        "C_m", "g_L", "E_e", "E_i", "Q_e", "Q_i", "tau_e", "tau_i", "K_e", "K_i", "N_e", "N_i",
+        "T", "E_L_e", "E_L_i", "tau_w_e", "tau_w_i", "b_i", "a_i", "cF_ee", "cF_ei", "cF_ie",
+        "cF_ii", "tau_OU", "sigma_OU", "w_noise", "muV0", "dmuV0", "sV0", "dsV0", "tN0", "dtN0",
+        "rate_max", "E_init", "I_init", "x_floor")] + [
+        ("P_e", C.c_double * 10), ("P_i", C.c_double * 10)]
+
+
+class vadx_run(C.Structure):
+    _fields_ = [("dt_ms", C.c_double), ("n_steps", C.c_int64), ("transient_steps", C.c_int64),
+                ("tavg_steps", C.c_int64), ("n_trace_steps", C.c_int64), ("seed", C.c_uint32),
+                ("integrator", C.c_int32), ("noise_off", C.c_int32), ("chunk_steps", C.c_int32)]
+
+
+class vadx_stats(C.Structure):
+    _fields_ = [(f, C.c_float) for f in STAT_NAMES] + [("flags", C.c_uint32),
+                                                        ("reserved", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libvadx.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -m paper_2311_13337_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P, vp = C.POINTER, C.c_void_p
+        st = C.c_int32
+        sig = {
+            "vadx_create": (st, [C.c_int, vp, P(vp)]),
+            "vadx_destroy": (None, [vp]),
+            "vadx_last_error": (C.c_char_p, [vp]),
+            "vadx_model_defaults": (st, [C.c_int, P(vadx_model)]),
+            "vadx_set_model": (st, [vp, P(vadx_model)]),
+            "vadx_add_connectome": (st, [vp, C.c_int32, vp, vp, P(C.c_int32)]),
+            "vadx_set_batch": (st, [vp, C.c_int64, vp, vp, vp, vp, vp]),
+            "vadx_set_trace": (st, [vp, C.c_int64, vp]),
+            "vadx_plan": (st, [vp, P(vadx_run), P(C.c_size_t)]),
+            "vadx_integrate": (st, [vp, P(vadx_run), vp, C.c_size_t]),
+            "vadx_sync": (st, [vp]),
+            "vadx_read_stats": (st, [vp, C.c_int64, C.c_int64, vp, C.c_int32]),
+            "vadx_read_fc": (st, [vp, C.c_int64, vp, C.c_int32]),
+            "vadx_read_samples": (st, [vp, C.c_int64, vp, C.c_int32]),
+            "vadx_read_state": (st, [vp, C.c_int64, vp, C.c_int32]),
+            "vadx_read_trace": (st, [vp, C.c_int64, vp, C.c_int32]),
+            "vadx_instance_shape": (st, [vp, C.c_int64, P(C.c_int32), P(C.c_int64)]),
+            "vadx_enable_timing": (st, [vp, C.c_int32]),
+            "vadx_kernel_time": (st, [vp, P(C.c_int64), P(C.c_double), P(C.c_int64),
+                                      P(C.c_double)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def vadx_model_defaults(preset: int = VADX_PRESET_LITERATURE_B) -> vadx_model:
+    m = vadx_model()
+    s = lib().vadx_model_defaults(preset, C.byref(m))
+    if s != VADX_OK:
+        raise VadxError(s, "bad preset")
+    return m
+
+
+class Context:
+    """One vadx_ctx bound to a device and a HIP stream (default: torch's
+    current stream on that device). Methods are the ABI calls."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(lib().vadx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def _check(self, s: int):
+        if s != VADX_OK:
+            msg = lib().vadx_last_error(getattr(self, "h", None)) if getattr(self, "h", None) else b""
+            raise VadxError(s, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vadx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vadx_set_model(self, m: vadx_model):
+        self._check(lib().vadx_set_model(self.h, C.byref(m)))
+
+    def vadx_add_connectome(self, weights: np.ndarray, tract_mm: np.ndarray) -> int:
+        w = np.ascontiguousarray(weights, np.float64)
+        L = np.ascontiguousarray(tract_mm, np.float64)
+        cid = C.c_int32()
+        self._check(lib().vadx_add_connectome(self.h, w.shape[0], _ptr(w), _ptr(L), C.byref(cid)))
+        return cid.value
+
+    def vadx_set_batch(self, S, b_e, a_e, v, conn=None):
+        arrs = [np.ascontiguousarray(x, np.float32) for x in (S, b_e, a_e, v)]
+        cp = None if conn is None else np.ascontiguousarray(conn, np.int32)
+        self._keep = (arrs, cp)
+        self._check(lib().vadx_set_batch(self.h, arrs[0].shape[0], *[_ptr(x) for x in arrs],
+                                         None if cp is None else _ptr(cp)))
+
+    def vadx_set_trace(self, inst):
+        a = np.ascontiguousarray(inst, np.int64)
+        self._check(lib().vadx_set_trace(self.h, a.shape[0], _ptr(a) if a.size else None))
+
+    def vadx_plan(self, run: vadx_run) -> int:
+        b = C.c_size_t()
+        self._check(lib().vadx_plan(self.h, C.byref(run), C.byref(b)))
+        return b.value
+
+    def vadx_integrate(self, run: vadx_run, ws_ptr: int, ws_bytes: int):
+        self._check(lib().vadx_integrate(self.h, C.byref(run), C.c_void_p(ws_ptr), ws_bytes))
+
+    def vadx_sync(self):
+        self._check(lib().vadx_sync(self.h))
+
+    def vadx_instance_shape(self, inst: int):
+        n, ns = C.c_int32(), C.c_int64()
+        self._check(lib().vadx_instance_shape(self.h, inst, C.byref(n), C.byref(ns)))
+        return n.value, ns.value
+
+    def vadx_read_stats(self, first: int, count: int) -> np.ndarray:
+        out = (vadx_stats * count)()
+        self._check(lib().vadx_read_stats(self.h, first, count, C.cast(out, C.c_void_p), VADX_HOST))
+        arr = np.ctypeslib.as_array(out).copy()
+        return arr
+
+    def _read(self, fn, inst, shape):
+        out = np.zeros(shape, np.float32)
+        self._check(getattr(lib(), fn)(self.h, inst, _ptr(out), VADX_HOST))
+        return out
+
+    def vadx_read_fc(self, inst: int) -> np.ndarray:
+        n, _ = self.vadx_instance_shape(inst)
+        return self._read("vadx_read_fc", inst, (n, n))
+
+    def vadx_read_samples(self, inst: int) -> np.ndarray:
+        n, ns = self.vadx_instance_shape(inst)
+        return self._read("vadx_read_samples", inst, (ns, n))
+
+    def vadx_read_state(self, inst: int) -> np.ndarray:
+        n, _ = self.vadx_instance_shape(inst)
+        return self._read("vadx_read_state", inst, (8, n))
+
+    def vadx_read_trace(self, slot: int, inst: int, n_trace_steps: int) -> np.ndarray:
+        n, _ = self.vadx_instance_shape(inst)
+        return self._read("vadx_read_trace", slot, (n_trace_steps, 8, n))
+
+    def vadx_enable_timing(self, on: bool = True):
+        self._check(lib().vadx_enable_timing(self.h, 1 if on else 0))
+
+    def vadx_kernel_time(self):
+        a, b, c, d = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
+        self._check(lib().vadx_kernel_time(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+
+def make_run(cfg, integrator: int = VADX_HEUN, noise_off: bool = False, chunk_steps: int = 0,
+             n_trace_steps=None) -> vadx_run:
+    """vadx_run from an object with dt_ms, n_steps, transient_steps, tavg_steps, seed."""
+    return vadx_run(dt_ms=cfg.dt_ms, n_steps=cfg.n_steps, transient_steps=cfg.transient_steps,
+                    tavg_steps=cfg.tavg_steps,
+                    n_trace_steps=cfg.n_trace_steps if n_trace_steps is None else n_trace_steps,
+                    seed=cfg.seed, integrator=integrator, noise_off=1 if noise_off else 0,
+                    chunk_steps=chunk_steps)
+
+
+class Sweep:
+    """Convenience driver: one context, connectomes, a batch, a planned run and
+    a torch-allocated workspace."""
+
+    def __init__(self, device: int = 0, model: vadx_model | None = None, stream=None):
+        import torch
+        self.torch = torch
+        self.ctx = Context(device, stream)
+        self.device = device
+        if model is not None:
+            self.ctx.vadx_set_model(model)
+        self.ws = None
+        self.run = None
+
+    def add_connectome(self, conn) -> int:
+        return self.ctx.vadx_add_connectome(conn.weights, conn.tract_mm)
+
+    def set_batch(self, batch, conn_ids=None):
+        conn = batch.conn if conn_ids is None else np.asarray(conn_ids)[batch.conn]
+        self.ctx.vadx_set_batch(batch.S, batch.b_e, batch.a_e, batch.v, conn)
+
+    def plan(self, run: vadx_run, trace=()):
+        self.ctx.vadx_set_trace(list(trace))
+        nbytes = self.ctx.vadx_plan(run)
+        if self.ws is None or self.ws.numel() < nbytes + 256:
+            self.ws = None
+            self.ws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8,
+                                       device=f"cuda:{self.device}")
+        self.run = run
+        self.nbytes = nbytes
+        return nbytes
+
+    def ws_ptr(self):
+        p = self.ws.data_ptr()
+        return (p + 255) // 256 * 256
+
+    def integrate(self):
+        self.ctx.vadx_integrate(self.run, self.ws_ptr(), self.nbytes)
+
+    def sync(self):
+        self.ctx.vadx_sync()
+
+    def stats(self, first: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = self.n_inst
+        s = self.ctx.vadx_read_stats(first, count)
+        return s
+
+    @property
+    def n_inst(self):
+        return len(self.ctx._keep[0][0])

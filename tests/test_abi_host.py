@@ -1,0 +1,53 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its model presets agree with the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2311_13337_amd import vadx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vadx.h")).read()
+    return sorted(set(re.findall(r"\b(vadx_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = vadx.lib()
+    names = _declared()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(vadx.EXPORTS) == names
+
+
+@pytest.mark.parametrize("preset", ["literature-B", "paper-T1"])
+def test_presets_match_oracle(oracle, preset):
+    g = vadx.vadx_model_defaults(vadx.PRESETS[preset])
+    o = oracle.model(preset)
+    for f, _ in vadx.vadx_model._fields_:
+        gv, ov = getattr(g, f), getattr(o, f)
+        if f in ("P_e", "P_i"):
+            assert list(gv) == list(ov), f
+        else:
+            assert gv == ov, f
+
+
+def test_bad_preset_rejected():
+    with pytest.raises(vadx.VadxError):
+        vadx.vadx_model_defaults(7)
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import ctypes as C
+    h = C.c_void_p()
+    s = vadx.lib().vadx_create(0, None, C.byref(h))
+    assert s in (vadx.VADX_E_HIP, vadx.VADX_E_ARG)
+    assert vadx.lib().vadx_last_error(None) == b"null context"
