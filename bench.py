@@ -1,0 +1,166 @@
+"""Benchmark of the TVB-AdEx sweep hot path on one MI355X.
+
+One step = one whole pass of the hot path over the uniform sweep: 4096
+parameter combinations (64 x 64 inclusive grid of S in [0, 0.5] x b_e in
+[0, 120], a_e = 0, v = 4 m/s) on one synthetic 68-region connectome, 100000
+steps of 0.1 ms (10 s) of stochastic Heun each, then the Pearson FC over the
+9000 post-transient 1 ms samples and the summary statistics. Inputs are
+resident on the GPU before timing starts. Prints one JSON line.
+
+The metric is instance-region-sim-s per wall-s: instances x regions x
+simulated seconds / wall seconds.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MI355X_FP32_VECTOR_TFLOPS = 157.3   # published FP32 vector peak (packed FMA)
+MI355X_HBM_GBPS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", choices=["uniform", "small"], default="uniform")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-instances", type=int, default=64)
+    p.add_argument("--cpu-sample-steps", type=int, default=10000)
+    p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_uniform.json"),
+                   help="HBM bytes per launch measured with rocprofv3 counters, if present")
+    return p.parse_args()
+
+
+def workload(name):
+    from paper_2311_13337_amd import inputs
+    conn = inputs.synthetic_connectome(68)
+    if name == "uniform":
+        return conn, inputs.grid_uniform(64, 64), inputs.RUN_UNIFORM, (
+            "uniform sweep: 64x64 grid of (S in [0,0.5], b_e in [0,120] pA), a_e=0, v=4 m/s; "
+            "4096 instances x 68 regions (synthetic connectome, 20% density, log-normal weights, "
+            "10-200 mm tracts); 100000 Heun steps of 0.1 ms (10 s); FC over 9000 1-ms samples "
+            "after a 1 s transient")
+    return conn, inputs.grid_small(), inputs.RUN_SMALL, (
+        "small grid: 8 combos (S in {0.1,0.3} x b_e in {0,60} x a_e in {0,4}), v=4 m/s, "
+        "68 regions, 10000 steps (1 s)")
+
+
+def cpu_baseline(conn, batch, cfg, n_inst, n_steps):
+    """The FP64 oracle on a bounded sample of the same workload (host cores)."""
+    import numpy as np
+
+    import oracle
+    from paper_2311_13337_amd import inputs
+    idx = np.linspace(0, len(batch) - 1, n_inst).round().astype(int)
+    sub = batch.subset(idx)
+    scfg = inputs.RunConfig(dt_ms=cfg.dt_ms, n_steps=n_steps, transient_steps=0,
+                            tavg_steps=cfg.tavg_steps, seed=cfg.seed)
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    oracle.run(oracle.model(), scfg, conn, sub, inst_ids=idx, n_threads=threads)
+    wall = time.perf_counter() - t0
+    units = n_inst * conn.n * n_steps * cfg.dt_ms / 1000.0
+    return {"value": units / wall, "unit": "instance-region-sim-s/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_inst} instances evenly spaced over the sweep x {n_steps} steps "
+                      f"({n_steps * cfg.dt_ms / 1000:.1f} s simulated), FP64, one instance per "
+                      f"thread, {wall:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the sweep on a single MI355X "
+              "(instances shard across GPUs without communication; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2311_13337_amd import vadx
+
+    conn, batch, cfg, desc = workload(args.workload)
+    sw = vadx.Sweep(0)
+    sw.add_connectome(conn)
+    sw.set_batch(batch)
+    run = vadx.make_run(cfg)
+    sw.plan(run)
+    ctx = sw.ctx
+    for _ in range(args.warmup):
+        sw.integrate()
+    torch.cuda.synchronize()
+    ctx.vadx_enable_timing(True)
+    ctx.vadx_kernel_time()                      # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sw.integrate()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_int, ms_int, n_fc, ms_fc = ctx.vadx_kernel_time()
+    ctx.vadx_enable_timing(False)
+    st = sw.stats()
+    assert np.isfinite(st["fc_mean"]).all(), "non-finite FC mean"
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    n_inst, n_reg = len(batch), conn.n
+    sim_s = cfg.n_steps * cfg.dt_ms / 1000.0
+    value = n_inst * n_reg * sim_s / (ms_per_step / 1000.0)
+
+    # roofline of the integration kernel: the kernel's own arithmetic per
+    # region-step (counted with an operation-counting scalar) plus 2 FLOPs per
+    # delayed-coupling edge, times the region-steps of one launch
+    f32, f64, trans = vadx.vadx_region_step_ops(vadx.VADX_HEUN)
+    nnz = int((conn.weights != 0).sum())
+    flop_rs = f32 + f64 + 2.0 * nnz / n_reg + 1.0
+    launches_per_step = n_int / args.steps
+    rs_per_launch = n_inst * n_reg * cfg.n_steps / launches_per_step
+    launch_ms = ms_int / n_int
+    achieved = flop_rs * rs_per_launch / (launch_ms / 1000.0) / 1e12
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        if tj.get("workload") == args.workload and tj.get("kernel_source_sha") == _src_sha():
+            traffic = tj.get("bytes_per_launch")
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
+            "traffic": traffic,
+            "kernel": "integrate_kernel", "flop_per_region_step": round(flop_rs, 1),
+            "transcendentals_per_region_step": trans,
+            "launch_ms_avg": round(launch_ms, 3), "launches_per_step": launches_per_step,
+            "fc_kernel_ms_per_step": round(ms_fc / max(n_fc, 1), 3)}
+    out = {"metric": "instance-region-sim-s per wall-s", "value": round(value, 1),
+           "unit": "instance-region-sim-s/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": desc, "instances": n_inst, "regions": n_reg,
+                      "steps_per_run": cfg.n_steps, "dt_ms": cfg.dt_ms,
+                      "parallelism": "single GPU"},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(conn, batch, cfg, args.cpu_sample_instances,
+                                           args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+def _src_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "adex_model.h", "engine.h"):
+        with open(os.path.join(ROOT, "paper_2311_13337_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -88,6 +88,9 @@ typedef struct vadx_run {
     int32_t integrator;   /* VADX_HEUN (default) or VADX_EULER */
     int32_t noise_off;
     int32_t chunk_steps;  /* steps per kernel launch; 0 = library default */
+    double fc_min_std;    /* kHz; a region whose rate std over the samples is
+                             below it is silent: zero variance and covariances,
+                             FC row 0 (diagonal 1), VADX_FLAG_ZERO_VAR set */
 } vadx_run;
 
 /* Summary statistics of one instance (definitions in vadx_read_stats). */
@@ -155,13 +158,14 @@ vadx_status vadx_sync(vadx_ctx *ctx);
  *  vadx_read_fc: the n x n FC matrix (float) of instance `inst`.
  *  vadx_read_samples: the [n_samples][n] rate samples (kHz) of `inst`.
  *  vadx_read_state: the final [8][n] state of `inst` (E, I, C_ee, C_ei, C_ii,
- *    W_e, W_i, OU).
+ *    W_e, W_i, OU) as doubles: the drift is evaluated in single precision and
+ *    the state accumulated in double precision.
  *  vadx_read_trace: [n_trace_steps][8][n] states of trace slot `slot`. */
 vadx_status vadx_read_stats(vadx_ctx *ctx, int64_t first, int64_t count, vadx_stats *out,
                             int32_t where);
 vadx_status vadx_read_fc(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
 vadx_status vadx_read_samples(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
-vadx_status vadx_read_state(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
+vadx_status vadx_read_state(vadx_ctx *ctx, int64_t inst, double *out, int32_t where);
 vadx_status vadx_read_trace(vadx_ctx *ctx, int64_t slot, float *out, int32_t where);
 
 /* Region count and number of post-transient samples of instance `inst` for
@@ -176,6 +180,15 @@ vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,
 vadx_status vadx_enable_timing(vadx_ctx *ctx, int32_t on);
 vadx_status vadx_kernel_time(vadx_ctx *ctx, int64_t *n_integrate_launches, double *integrate_ms,
                              int64_t *n_fc_launches, double *fc_ms);
+
+/* Arithmetic of one region-step in this library's formulation, counted by
+ * running the kernel's own model code with an operation-counting scalar:
+ * single- and double-precision FLOPs (add, mul = 1, fma = 2, transcendental =
+ * 1) and the number of transcendentals among them. The delayed-coupling sum
+ * adds 2 FLOPs per connectome edge and step on top (not included). For
+ * roofline accounting. */
+vadx_status vadx_region_step_ops(int32_t integrator, double *flop32, double *flop64,
+                                 double *transcendental);
 
 #ifdef __cplusplus
 }

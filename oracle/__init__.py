@@ -57,7 +57,7 @@ class Model(C.Structure):
 class RunCfg(C.Structure):
     _fields_ = [("dt", C.c_double), ("n_steps", C.c_int64), ("transient_steps", C.c_int64),
                 ("tavg_steps", C.c_int64), ("n_trace_steps", C.c_int64), ("seed", C.c_uint32),
-                ("integrator", C.c_int32), ("noise_off", C.c_int32)]
+                ("integrator", C.c_int32), ("noise_off", C.c_int32), ("fc_min_std", C.c_double)]
 
 
 _lib = None
@@ -81,7 +81,7 @@ def lib():
         L.oracle_normal.restype = C.c_double
         L.oracle_normalise_rows.argtypes = [C.c_int, dp, dp]
         L.oracle_delays.argtypes = [C.c_int, dp, C.c_float, C.c_double, ip]
-        L.oracle_fc_stats.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp]
+        L.oracle_fc_stats.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_double, dp, dp]
         L.oracle_fc_stats.restype = C.c_uint32
         L.oracle_step_region.argtypes = [P(Model), C.c_int, C.c_double, dp, C.c_double, C.c_double,
                                          C.c_double, C.c_double]
@@ -150,13 +150,13 @@ def delays(L, v: float, dt: float) -> np.ndarray:
     return out
 
 
-def fc_stats(samples, w_raw):
+def fc_stats(samples, w_raw, min_std=0.0):
     x = np.ascontiguousarray(samples, np.float64)
     w = np.ascontiguousarray(w_raw, np.float64)
     n = w.shape[0]
     fc = np.zeros((n, n))
     st = np.zeros(6)
-    flags = lib().oracle_fc_stats(n, x.shape[0], x, w, fc, st)
+    flags = lib().oracle_fc_stats(n, x.shape[0], x, w, min_std, fc, st)
     return fc, st, flags
 
 
@@ -178,7 +178,8 @@ def run(m: Model, run_cfg, conn, batch, inst_ids=None, n_trace_steps=None, want_
     nt = run_cfg.n_trace_steps if n_trace_steps is None else n_trace_steps
     r = RunCfg(dt=run_cfg.dt_ms, n_steps=run_cfg.n_steps, transient_steps=run_cfg.transient_steps,
                tavg_steps=run_cfg.tavg_steps, n_trace_steps=nt, seed=run_cfg.seed,
-               integrator=integrator, noise_off=1 if noise_off else 0)
+               integrator=integrator, noise_off=1 if noise_off else 0,
+               fc_min_std=getattr(run_cfg, "fc_min_std", 1e-9))
     ns = (run_cfg.n_steps - run_cfg.transient_steps) // run_cfg.tavg_steps
     ids = np.arange(ni, dtype=np.uint32) if inst_ids is None else np.asarray(inst_ids, np.uint32)
     out = {

@@ -75,7 +75,7 @@ int oracle_model_preset(int preset, or_model *m)
     m->tau_OU = 5.0;  m->sigma_OU = 1e-3; m->w_noise = 1e-3;
     m->muV0 = -60.0;  m->dmuV0 = 10.0; m->sV0 = 4.0; m->dsV0 = 6.0;
     m->tN0 = 0.5;     m->dtN0 = 1.0;
-    m->rate_max = 1.0; m->E_init = 0.01; m->I_init = 0.01;
+    m->rate_max = 1.0; m->E_init = 0.004; m->I_init = 0.01;
     /* minimum input rate of the transfer function (kHz): spontaneous release */
     m->x_floor = 1e-6;
     memcpy(m->P_e, T1_RS, sizeof(T1_RS));
@@ -391,9 +391,12 @@ void oracle_delays(int n, const double *L, float v, double dt, int32_t *d)
 enum { FLAG_NONFINITE = 1u, FLAG_CLAMP = 2u, FLAG_ZERO_VAR = 4u };
 
 /* x: [ns][n] samples (kHz). w_raw: [n][n] raw SC. Outputs fc [n][n] and
-   stats = {fc_mean, fc_std, fc_sc_corr, rate_mean_hz, rate_std_hz, sync_index}. */
+   stats = {fc_mean, fc_std, fc_sc_corr, rate_mean_hz, rate_std_hz, sync_index}.
+   A region whose temporal standard deviation is below min_std (kHz) is silent:
+   its variance and covariances count as zero, its FC entries are zero (one on
+   the diagonal) and the zero-variance flag is set. */
 uint32_t oracle_fc_stats(int n, int64_t ns, const double *x, const double *w_raw,
-                         double *fc, double *stats)
+                         double min_std, double *fc, double *stats)
 {
     uint32_t flags = 0;
     double *mean = calloc((size_t)n, sizeof(double));
@@ -406,6 +409,9 @@ uint32_t oracle_fc_stats(int n, int64_t ns, const double *x, const double *w_raw
             for (int l = 0; l < n; ++l)
                 cov[k * n + l] += (x[s * n + k] - mean[k]) * (x[s * n + l] - mean[l]);
     for (int i = 0; i < n * n; ++i) cov[i] = ns > 0 ? cov[i] / (double)ns : 0.0;
+    for (int k = 0; k < n; ++k)
+        if (cov[k * n + k] < min_std * min_std)
+            for (int l = 0; l < n; ++l) { cov[k * n + l] = 0.0; cov[l * n + k] = 0.0; }
     for (int k = 0; k < n; ++k)
         for (int l = 0; l < n; ++l) {
             double vk = cov[k * n + k], vl = cov[l * n + l];
@@ -505,6 +511,7 @@ typedef struct {
     uint32_t seed;
     int32_t integrator;
     int32_t noise_off; /* 1: z = 0 (deterministic runs for pins) */
+    double fc_min_std; /* silence threshold of the FC (kHz) */
 } or_run;
 
 typedef struct {
@@ -591,7 +598,7 @@ static void run_instance(run_job *J, int64_t q)
     if (J->fc || J->stats) {
         double *fc = J->fc ? J->fc + (size_t)q * n * n : malloc(sizeof(double) * n * n);
         double st[6];
-        flags |= oracle_fc_stats(n, ns, smp, J->w_raw, fc, st);
+        flags |= oracle_fc_stats(n, ns, smp, J->w_raw, r->fc_min_std, fc, st);
         if (J->stats) memcpy(J->stats + q * 6, st, sizeof(st));
         if (!J->fc) free(fc);
     }

@@ -16,6 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvadx.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "vadx_api.cpp")]
+HOST_SOURCES = [os.path.join(CSRC, "opcount.cpp")]   # plain C++ (g++), no device code
 ARCH = os.environ.get("VADX_OFFLOAD_ARCH", "gfx950")
 
 
@@ -45,6 +46,15 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}")
         if verbose:
             sys.stderr.write(r.stderr)
+        objs.append(obj)
+    for src in HOST_SOURCES:
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+               "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"g++ failed on {src}")
         objs.append(obj)
     tmp = LIB + ".tmp"
     r = subprocess.run([hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs],

@@ -95,6 +95,7 @@ VADX_HD float lg2(float x)
     return __builtin_log2f(x);
 #endif
 }
+VADX_HD double sqr(double x) { return __builtin_sqrt(x); }
 VADX_HD float fmaf_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 VADX_HD float absf_(float x) { return __builtin_fabsf(x); }
 VADX_HD float selectf(bool c, float a, float b) { return c ? a : b; }
@@ -219,22 +220,29 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
     T di = rcp(fmaf_(T(M.Cm), r, T(M.tau_i)));
     T qe = de * r, qi = di * r;
     T he1 = T(M.Cm) * qe * qe, hi1 = T(M.Cm) * qi * qi;
-    Jet<T> De = jofG(de, he1, T(-2) * T(M.tau_e) * he1 * qe, aE, aI);
-    Jet<T> Di = jofG(di, hi1, T(-2) * T(M.tau_i) * hi1 * qi, aE, aI);
+    const T he2 = T(-2) * T(M.tau_e) * he1 * qe, hi2 = T(-2) * T(M.tau_i) * hi1 * qi;
+    Jet<T> De = jofG(de, he1, he2, aE, aI);
+    Jet<T> Di = jofG(di, hi1, hi2, aE, aI);
     Jet<T> S2 = jadd(jmul(Ae, De), jmul(Ai, Di));   // 2 sigma_V^2
     Jet<T> As = jadd(Ae, Ai);
     // q = S2^(-1/2) = 1/(sqrt2 sigma_V);  (x^-1/2)' = -q^3/2, '' = 3 q^5/4
     T q = rsq(S2.v);
     T q2 = q * q, q3 = q2 * q;
     Jet<T> Q = jchain(S2, q, T(-0.5f) * q3, T(0.75f) * q3 * q2);
-    // sigma_V = S2 q / sqrt2 ; tau_V = As q^2 ; 1/tau_V = S2 / As
+    // sigma_V = S2 q / sqrt2
     Jet<T> SQ = jmul(S2, Q);
-    Jet<T> Q2 = jsq(Q);
-    Jet<T> TV = jmul(As, Q2);
+    // 1/tau_V = (A_e d_e + A_i d_i)/(A_e + A_i) = d_e + w (d_i - d_e) with
+    // w = A_i/(A_e + A_i): a weighted mean of d_e, d_i whose derivatives do not
+    // cancel when one source dominates (the ratio form loses them in FP32).
     T ra = rcp(As.v);
     T ra2 = ra * ra;
     Jet<T> RA = jchain(As, ra, -ra2, T(2) * ra2 * ra);
-    Jet<T> ITV = jmul(S2, RA);                       // 1/tau_V
+    Jet<T> Wi = jmul(Ai, RA);
+    Jet<T> Dd = jofG(di - de, hi1 - he1, hi2 - he2, aE, aI);
+    Jet<T> ITV = jadd(De, jmul(Wi, Dd));             // 1/tau_V
+    T itv = rcp(ITV.v);
+    T itv2 = itv * itv;
+    Jet<T> TV = jchain(ITV, itv, -itv2, T(2) * itv2 * itv);
     // normalised polynomial coordinates
     Jet<T> mm = jaffine(MU, T(M.mu_s), T(M.mu_o));
     Jet<T> ss = jaffine(SQ, T(M.sg_s), T(M.sg_o));   // sg_s includes 1/sqrt2
@@ -318,24 +326,30 @@ template <class T> VADX_HD bool project(const KModel &M, T X[8])
     return hit;
 }
 
-// One step of stochastic Heun (or Euler-Maruyama) for one region. gdw is the
-// OU increment (sigma/tau_OU) sqrt(dt) z. Returns true when a bound was hit.
-template <class T>
-VADX_HD bool step_region(const KModel &M, int integrator, T dt, T X[8], T c, T be, T ae, T gdw)
+// One step of stochastic Heun (or Euler-Maruyama) for one region. The drift
+// is evaluated in T (float); the state X and its increments are accumulated
+// in S (double), so the rounding of the state does not build up over the
+// run. gdw is the OU increment (sigma/tau_OU) sqrt(dt) z. Returns true when a
+// bound was hit.
+template <class T, class S>
+VADX_HD bool step_region(const KModel &M, int integrator, S dt, S X[8], T c, T be, T ae, S gdw)
 {
-    T f0[8], f1[8], Xt[8];
-    drift(M, X, c, be, ae, f0);
+    T xf[8], f0[8], f1[8];
+    S Xt[8];
+    for (int q = 0; q < 8; ++q) xf[q] = T(X[q]);
+    drift(M, xf, c, be, ae, f0);
     if (integrator == 1) {
-        for (int q = 0; q < 8; ++q) X[q] = fmaf_(dt, f0[q], X[q]);
+        for (int q = 0; q < 8; ++q) X[q] = X[q] + dt * S(f0[q]);
         X[7] = X[7] + gdw;
         return project(M, X);
     }
-    for (int q = 0; q < 8; ++q) Xt[q] = fmaf_(dt, f0[q], X[q]);
+    for (int q = 0; q < 8; ++q) Xt[q] = X[q] + dt * S(f0[q]);
     Xt[7] = Xt[7] + gdw;
     bool hit = project(M, Xt);
-    drift(M, Xt, c, be, ae, f1);
-    const T hdt = T(0.5f) * dt;
-    for (int q = 0; q < 8; ++q) X[q] = fmaf_(hdt, f0[q] + f1[q], X[q]);
+    for (int q = 0; q < 8; ++q) xf[q] = T(Xt[q]);
+    drift(M, xf, c, be, ae, f1);
+    const S hdt = S(0.5) * dt;
+    for (int q = 0; q < 8; ++q) X[q] = X[q] + hdt * (S(f0[q]) + S(f1[q]));
     X[7] = X[7] + gdw;
     hit = project(M, X) || hit;
     return hit;

@@ -23,7 +23,7 @@ struct InstDev {
     int32_t pad;
     int64_t table_off;  // into the packed delay tables (nnz entries)
     int64_t trace_off;  // floats: [n_trace][8][n]; -1: not traced
-    int64_t state_off;  // floats: [8][n] final/resume state
+    int64_t state_off;  // floats (8-byte aligned): [8][n] doubles, final/resume state
     int64_t acc_off;    // floats: [n] running time-average sums
     int64_t ring_off;   // floats: [n][D] excitatory-rate history
     int64_t samp_off;   // floats: [n_samples][n]
@@ -65,7 +65,8 @@ struct IntegrateArgs {
     uint32_t *flags;            // per instance
     int64_t n_steps_total, transient_steps, tavg_steps, n_trace_steps, n_samples;
     int64_t n_begin, n_end;
-    float dt, gdw_scale;        // gdw_scale = sigma_OU / tau_OU * sqrt(dt) (0: noise off)
+    double dt, gdw_scale;       // gdw_scale = sigma_OU / tau_OU * sqrt(dt) (0: noise off)
+    double E_init, I_init;
     uint32_t seed;
     int32_t integrator;
     int32_t block;              // steps per barrier block (<= kMaxBlock)
@@ -79,6 +80,7 @@ struct FcArgs {
     float *stats;               // [inst][8] as vadx_stats (6 floats + flags + reserved)
     uint32_t *flags;
     int64_t n_samples;
+    double min_var;             // silence threshold on a region's variance
 };
 
 // Launchers (return hipError_t of the launch).

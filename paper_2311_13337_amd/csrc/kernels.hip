@@ -142,7 +142,7 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 
     InstDev I;
     ConnDev C;
-    float X[8];
+    double X[8];
     float acc = 0.f;
     int row_b = 0, row_e = 0;
     const float *wrow = nullptr;
@@ -163,14 +163,15 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
         tc = a.n_begin % a.tavg_steps;
         sidx = a.n_begin / a.tavg_steps - a.transient_steps / a.tavg_steps;
         if (a.n_begin == 0) {
-            X[0] = a.M.E_init;
-            X[1] = a.M.I_init;
+            X[0] = a.E_init;
+            X[1] = a.I_init;
 #pragma unroll
-            for (int q = 2; q < 8; ++q) X[q] = 0.f;
+            for (int q = 2; q < 8; ++q) X[q] = 0.0;
             float *rr = ring + (int64_t)k * I.D;
-            for (int s = 0; s < I.D; ++s) rr[s] = a.M.E_init;
+            const float e0 = (float)a.E_init;
+            for (int s = 0; s < I.D; ++s) rr[s] = e0;
         } else {
-            const float *st = a.ws + I.state_off;
+            const double *st = reinterpret_cast<const double *>(a.ws + I.state_off);
 #pragma unroll
             for (int q = 0; q < 8; ++q) X[q] = st[q * I.n + k];
             acc = a.ws[I.acc_off + k];
@@ -218,16 +219,18 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
                     normals4(a.seed, I.id, (uint32_t)(n >> 2), (uint32_t)k, z4);
                 const float z = r == 0 ? z4[0] : (r == 1 ? z4[1] : (r == 2 ? z4[2] : z4[3]));
                 const float c = cbuf[b * nthr + tid];
-                bool hit = step_region(a.M, a.integrator, a.dt, X, c, be, ae, a.gdw_scale * z);
-                float chk = ((X[0] + X[1]) + (X[2] + X[3])) + ((X[4] + X[5]) + (X[6] + X[7]));
+                bool hit = step_region(a.M, a.integrator, a.dt, X, c, be, ae,
+                                       a.gdw_scale * (double)z);
+                double chk = ((X[0] + X[1]) + (X[2] + X[3])) + ((X[4] + X[5]) + (X[6] + X[7]));
                 fl |= hit ? 2u : 0u;
                 fl |= __builtin_isfinite(chk) ? 0u : 1u;
                 // history of E: slot (n + 1) mod D
                 wm += 1;
                 wm -= (wm >= D) ? D : 0;
-                myrow[wm] = X[0];
+                const float e1 = (float)X[0];
+                myrow[wm] = e1;
                 // time average
-                acc += X[0];
+                acc += e1;
                 tc += 1;
                 if (tc == a.tavg_steps) {
                     if (sidx >= 0 && sidx < a.n_samples)
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
                 if (trace != nullptr && n < a.n_trace_steps) {
                     float *tr = trace + n * 8 * I.n + k;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) tr[q * I.n] = X[q];
+                    for (int q = 0; q < 8; ++q) tr[q * I.n] = (float)X[q];
                 }
             }
             nm += nb;
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
         __syncthreads();   // this block's history visible before the next block reads it
     }
     if (active) {
-        float *st = a.ws + I.state_off;
+        double *st = reinterpret_cast<double *>(a.ws + I.state_off);
 #pragma unroll
         for (int q = 0; q < 8; ++q) st[q * I.n + k] = X[q];
         a.ws[I.acc_off + k] = acc;
@@ -324,7 +327,8 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
         double m1 = s1 * inv_ns;
         shift[k] = sh;
         mean[k] = m1;   // mean of the shifted samples
-        var[k] = ns > 0 ? s2 * inv_ns - m1 * m1 : 0.0;
+        const double vk = ns > 0 ? s2 * inv_ns - m1 * m1 : 0.0;
+        var[k] = vk < a.min_var ? 0.0 : vk;   // silent regions: zero variance
     }
     __syncthreads();
 
@@ -388,7 +392,8 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
                         s_cov += var[k];
                         continue;
                     }
-                    const double cov = P[i][j] * inv_ns - mean[k] * mean[l];
+                    const double cov = (var[k] > 0.0 && var[l] > 0.0)
+                                           ? P[i][j] * inv_ns - mean[k] * mean[l] : 0.0;
                     const double f = (var[k] > 0.0 && var[l] > 0.0) ? cov / sqrt(var[k] * var[l])
                                                                     : 0.0;
                     fc[(int64_t)k * n + l] = (float)f;

@@ -1,0 +1,90 @@
+// opcount.cpp -- exact arithmetic count of one region-step of the integration
+// kernel, obtained by running the same templated model code (adex_model.h) on
+// the host with a scalar type that counts its operations. Used for roofline
+// accounting: add/sub/mul/compare-free min-max = 1 FLOP, fused multiply-add =
+// 2 FLOPs, each transcendental (reciprocal, (reciprocal) square root, exp2,
+// log2) = 1 FLOP and also tallied on its own.
+#include <cmath>
+#include <cstdint>
+
+#include "vadx.h"
+
+namespace vadx {
+struct OpTally {
+    double flop32 = 0, flop64 = 0, trans32 = 0, trans64 = 0;
+};
+static thread_local OpTally g_tally;
+
+template <class U> struct Cnt {
+    U v;
+    Cnt() : v(0) {}
+    Cnt(double x) : v((U)x) {}
+    template <class V> explicit Cnt(const Cnt<V> &o) : v((U)o.v) {}
+    static void flop(double n) { (sizeof(U) == 8 ? g_tally.flop64 : g_tally.flop32) += n; }
+    static void trans() { (sizeof(U) == 8 ? g_tally.trans64 : g_tally.trans32) += 1; flop(1); }
+};
+template <class U> Cnt<U> mk(U x) { Cnt<U> r; r.v = x; return r; }
+template <class U> Cnt<U> operator+(Cnt<U> a, Cnt<U> b) { Cnt<U>::flop(1); return mk<U>(a.v + b.v); }
+template <class U> Cnt<U> operator-(Cnt<U> a, Cnt<U> b) { Cnt<U>::flop(1); return mk<U>(a.v - b.v); }
+template <class U> Cnt<U> operator*(Cnt<U> a, Cnt<U> b) { Cnt<U>::flop(1); return mk<U>(a.v * b.v); }
+template <class U> Cnt<U> operator-(Cnt<U> a) { return mk<U>(-a.v); }
+template <class U> bool operator<(Cnt<U> a, Cnt<U> b) { return a.v < b.v; }
+template <class U> bool operator>(Cnt<U> a, Cnt<U> b) { return a.v > b.v; }
+template <class U> bool operator>=(Cnt<U> a, Cnt<U> b) { return a.v >= b.v; }
+
+using CF = Cnt<float>;
+using CD = Cnt<double>;
+inline CF rcp(CF x) { CF::trans(); return mk<float>(1.0f / x.v); }
+inline CF rsq(CF x) { CF::trans(); return mk<float>(1.0f / std::sqrt(x.v)); }
+inline CF sqr(CF x) { CF::trans(); return mk<float>(std::sqrt(x.v)); }
+inline CD sqr(CD x) { CD::trans(); return mk<double>(std::sqrt(x.v)); }
+inline CF ex2(CF x) { CF::trans(); return mk<float>(std::exp2(x.v)); }
+inline CF lg2(CF x) { CF::trans(); return mk<float>(std::log2(x.v)); }
+inline CF fmaf_(CF a, CF b, CF c) { CF::flop(2); return mk<float>(std::fma(a.v, b.v, c.v)); }
+inline CF absf_(CF x) { return mk<float>(std::fabs(x.v)); }
+inline CF selectf(bool c, CF a, CF b) { return c ? a : b; }
+inline CF maxf_(CF a, CF b) { CF::flop(1); return mk<float>(std::fmax(a.v, b.v)); }
+} // namespace vadx
+
+#include "adex_model.h"
+
+namespace vadx {
+static KModel count_model()
+{
+    vadx_model m;
+    vadx_model_defaults(VADX_PRESET_LITERATURE_B, &m);
+    KModel k{};
+    k.aE = 3000.f; k.aI = 2500.f; k.gL = 10.f; k.Cm = 200.f; k.Ee = 0.f; k.Ei = -80.f;
+    k.Qe = 1.5f; k.Qi = 5.f; k.tau_e = 5.f; k.tau_i = 5.f; k.KeTe2 = 1e4f; k.KiTi2 = 2500.f;
+    k.EL[0] = -64.f; k.EL[1] = -65.f; k.gLEL[0] = -640.f; k.gLEL[1] = -650.f;
+    for (int i = 0; i < 10; ++i) { k.P[0][i] = (float)m.P_e[i]; k.P[1][i] = (float)m.P_i[i]; }
+    k.mu_s = 0.1f; k.mu_o = 6.f; k.sg_s = 0.11785f; k.sg_o = -0.6667f; k.tn_s = 0.05f;
+    k.tn_o = -0.5f; k.invT = 0.05f; k.invNe = 1.25e-4f; k.invNi = 5e-4f;
+    k.inv_tauw[0] = 0.002f; k.inv_tauw[1] = 1.f; k.cF[0][0] = k.cF[1][0] = 3e-4f;
+    k.inv_tauOU = 0.2f; k.ou_gain = 2e-4f; k.w_noise = 1e-3f; k.rate_max = 1.f;
+    k.x_floor = 1e-6f; k.E_init = 0.004f; k.I_init = 0.01f;
+    return k;
+}
+} // namespace vadx
+
+extern "C" vadx_status vadx_region_step_ops(int32_t integrator, double *flop32, double *flop64,
+                                            double *transcendental)
+{
+    using namespace vadx;
+    if (!flop32 || !flop64 || !transcendental || (integrator != 0 && integrator != 1))
+        return VADX_E_ARG;
+    g_tally = OpTally{};
+    KModel M = count_model();
+    CD X[8] = {CD(0.004), CD(0.01), CD(2e-6), CD(4e-6), CD(1e-5), CD(20.0), CD(0.0), CD(1e-4)};
+    step_region<CF, CD>(M, integrator, CD(0.1), X, CF(1e-3f), CF(30.f), CF(2.f), CD(1e-5));
+    // per-step extras of the kernel: coupling scale S*c, OU increment gdw*z, the
+    // running time average, and one quarter of a Box-Muller pair evaluation
+    // (two normals per pair: log, sqrt, sin, cos and 8 products/sums).
+    g_tally.flop32 += 1 + 1 + 0.25 * (8 + 4);
+    g_tally.flop64 += 1;
+    g_tally.trans32 += 0.25 * 4;
+    *flop32 = g_tally.flop32;
+    *flop64 = g_tally.flop64;
+    *transcendental = g_tally.trans32 + g_tally.trans64;
+    return VADX_OK;
+}

@@ -101,6 +101,9 @@ struct vadx_ctx {
     int wg_instances_override = 0;
 };
 
+// Errors of calls made without a context (vadx_create) land here.
+static thread_local std::string g_err = "";
+
 static vadx_status fail(vadx_ctx *c, vadx_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -109,6 +112,7 @@ static vadx_status fail(vadx_ctx *c, vadx_status st, const char *fmt, ...)
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
     if (c) c->err = buf;
+    else g_err = buf;
     return st;
 }
 
@@ -138,7 +142,7 @@ vadx_status vadx_model_defaults(int preset, vadx_model *m)
     m->cF_ee = 0.3e-3; m->cF_ei = 0.0; m->cF_ie = 0.3e-3; m->cF_ii = 0.0;
     m->tau_OU = 5.0; m->sigma_OU = 1e-3; m->w_noise = 1e-3;
     m->muV0 = -60.0; m->dmuV0 = 10.0; m->sV0 = 4.0; m->dsV0 = 6.0; m->tN0 = 0.5; m->dtN0 = 1.0;
-    m->rate_max = 1.0; m->E_init = 0.01; m->I_init = 0.01; m->x_floor = 1e-6;
+    m->rate_max = 1.0; m->E_init = 0.004; m->I_init = 0.01; m->x_floor = 1e-6;
     std::memcpy(m->P_e, kRS, sizeof(kRS));
     std::memcpy(m->P_i, kFS, sizeof(kFS));
     if (preset == VADX_PRESET_LITERATURE_B) {
@@ -152,12 +156,15 @@ vadx_status vadx_model_defaults(int preset, vadx_model *m)
 
 vadx_status vadx_create(int device, void *hip_stream, vadx_ctx **out)
 {
-    if (!out) return VADX_E_ARG;
+    if (!out) return fail(nullptr, VADX_E_ARG, "null output");
     *out = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return VADX_E_HIP;
-    if (device < 0 || device >= ndev) return VADX_E_ARG;
-    if (hipSetDevice(device) != hipSuccess) return VADX_E_HIP;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0)
+        return fail(nullptr, VADX_E_HIP, "hipGetDeviceCount: %s (%d devices)", hipGetErrorString(e), ndev);
+    if (device < 0 || device >= ndev) return fail(nullptr, VADX_E_ARG, "device %d out of range", device);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, VADX_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
     vadx_ctx *c = new vadx_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -182,7 +189,7 @@ void vadx_destroy(vadx_ctx *c)
 
 const char *vadx_last_error(const vadx_ctx *c)
 {
-    if (!c) return "null context";
+    if (!c) return g_err.c_str();
     return c->err.c_str();
 }
 
@@ -340,6 +347,7 @@ static bool run_ok(vadx_ctx *c, const vadx_run *r)
     if (r->transient_steps > r->n_steps) return false;
     if (r->integrator != VADX_HEUN && r->integrator != VADX_EULER) return false;
     if (r->chunk_steps < 0) return false;
+    if (!(std::isfinite(r->fc_min_std) && r->fc_min_std >= 0.0)) return false;
     (void)c;
     return true;
 }
@@ -433,7 +441,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         d.id = (uint32_t)i;
         d.table_off = c->h_tables[tab_of[i]].off;
         d.trace_off = -1;
-        d.state_off = f_state; f_state += 8LL * hc.n;
+        d.state_off = f_state; f_state += 16LL * hc.n;   // 8 doubles per region
         d.acc_off = f_acc; f_acc += hc.n;
         d.ring_off = f_ring; f_ring += (int64_t)hc.n * d.D;
         d.samp_off = f_samp; f_samp += (ns > 0 ? ns : 0) * hc.n;
@@ -548,8 +556,10 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
     a.tavg_steps = r->tavg_steps;
     a.n_trace_steps = r->n_trace_steps;
     a.n_samples = c->n_samples;
-    a.dt = (float)r->dt_ms;
-    a.gdw_scale = r->noise_off ? 0.0f : (float)(c->model.sigma_OU / c->model.tau_OU * std::sqrt(r->dt_ms));
+    a.dt = r->dt_ms;
+    a.gdw_scale = r->noise_off ? 0.0 : c->model.sigma_OU / c->model.tau_OU * std::sqrt(r->dt_ms);
+    a.E_init = c->model.E_init;
+    a.I_init = c->model.I_init;
     a.seed = r->seed;
     a.integrator = r->integrator;
     a.block = c->block;
@@ -575,6 +585,7 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
     f.stats = (float *)((char *)ws + c->off_stats);
     f.flags = flags;
     f.n_samples = c->n_samples;
+    f.min_var = r->fc_min_std * r->fc_min_std;
     hipEvent_t stop = nullptr;
     if (c->timing) { vadx_status st = record(c, c->ev_fc, &stop); if (st) return st; }
     HIP_TRY(c, launch_fc_stats(f, ni, c->stream));
@@ -641,14 +652,14 @@ vadx_status vadx_read_samples(vadx_ctx *c, int64_t inst, float *out, int32_t whe
     return copy_out(c, out, (float *)c->ws + d.samp_off, sizeof(float) * d.n * c->n_samples, where);
 }
 
-vadx_status vadx_read_state(vadx_ctx *c, int64_t inst, float *out, int32_t where)
+vadx_status vadx_read_state(vadx_ctx *c, int64_t inst, double *out, int32_t where)
 {
     if (!c) return VADX_E_ARG;
     vadx_status st = check_read(c, inst, out);
     if (st) return st;
     const InstDev &d = c->h_inst[inst];
     if (c->plan_run.n_steps == 0) return fail(c, VADX_E_STATE, "no steps were integrated");
-    return copy_out(c, out, (float *)c->ws + d.state_off, sizeof(float) * 8 * d.n, where);
+    return copy_out(c, out, (float *)c->ws + d.state_off, sizeof(double) * 8 * d.n, where);
 }
 
 vadx_status vadx_read_trace(vadx_ctx *c, int64_t slot, float *out, int32_t where)

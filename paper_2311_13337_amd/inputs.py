@@ -152,6 +152,7 @@ class RunConfig:
     tavg_steps: int = 10
     seed: int = 0
     n_trace_steps: int = 0
+    fc_min_std: float = 1e-9   # kHz: regions with a smaller rate std are silent
 
     @property
     def n_samples(self) -> int:

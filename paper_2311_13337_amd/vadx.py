@@ -27,7 +27,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_set_model", "vadx_add_connectome", "vadx_set_batch", "vadx_set_trace",
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
-           "vadx_enable_timing", "vadx_kernel_time")
+           "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops")
 
 
 class VadxError(RuntimeError):
@@ -48,7 +48,8 @@ class vadx_model(C.Structure):
 class vadx_run(C.Structure):
     _fields_ = [("dt_ms", C.c_double), ("n_steps", C.c_int64), ("transient_steps", C.c_int64),
                 ("tavg_steps", C.c_int64), ("n_trace_steps", C.c_int64), ("seed", C.c_uint32),
-                ("integrator", C.c_int32), ("noise_off", C.c_int32), ("chunk_steps", C.c_int32)]
+                ("integrator", C.c_int32), ("noise_off", C.c_int32), ("chunk_steps", C.c_int32),
+                ("fc_min_std", C.c_double)]
 
 
 class vadx_stats(C.Structure):
@@ -66,6 +67,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it first "
                                "(python -m paper_2311_13337_amd.build)")
+        # The library and PyTorch must share one HIP runtime (the stream and
+        # workspace come from PyTorch): load PyTorch's runtime first so the
+        # library's libamdhip64 dependency resolves to it.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P, vp = C.POINTER, C.c_void_p
         st = C.c_int32
@@ -90,6 +95,8 @@ def lib():
             "vadx_enable_timing": (st, [vp, C.c_int32]),
             "vadx_kernel_time": (st, [vp, P(C.c_int64), P(C.c_double), P(C.c_int64),
                                       P(C.c_double)]),
+            "vadx_region_step_ops": (st, [C.c_int32, P(C.c_double), P(C.c_double),
+                                          P(C.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -101,6 +108,15 @@ def lib():
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def vadx_region_step_ops(integrator: int = VADX_HEUN):
+    """(fp32 FLOPs, fp64 FLOPs, transcendentals) of one region-step, coupling excluded."""
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    s = lib().vadx_region_step_ops(integrator, C.byref(a), C.byref(b), C.byref(c))
+    if s != VADX_OK:
+        raise VadxError(s, "bad integrator")
+    return a.value, b.value, c.value
 
 
 def vadx_model_defaults(preset: int = VADX_PRESET_LITERATURE_B) -> vadx_model:
@@ -127,7 +143,7 @@ class Context:
 
     def _check(self, s: int):
         if s != VADX_OK:
-            msg = lib().vadx_last_error(getattr(self, "h", None)) if getattr(self, "h", None) else b""
+            msg = lib().vadx_last_error(getattr(self, "h", None))
             raise VadxError(s, (msg or b"").decode())
 
     def close(self):
@@ -199,7 +215,9 @@ class Context:
 
     def vadx_read_state(self, inst: int) -> np.ndarray:
         n, _ = self.vadx_instance_shape(inst)
-        return self._read("vadx_read_state", inst, (8, n))
+        out = np.zeros((8, n), np.float64)
+        self._check(lib().vadx_read_state(self.h, inst, _ptr(out), VADX_HOST))
+        return out
 
     def vadx_read_trace(self, slot: int, inst: int, n_trace_steps: int) -> np.ndarray:
         n, _ = self.vadx_instance_shape(inst)
@@ -221,7 +239,7 @@ def make_run(cfg, integrator: int = VADX_HEUN, noise_off: bool = False, chunk_st
                     tavg_steps=cfg.tavg_steps,
                     n_trace_steps=cfg.n_trace_steps if n_trace_steps is None else n_trace_steps,
                     seed=cfg.seed, integrator=integrator, noise_off=1 if noise_off else 0,
-                    chunk_steps=chunk_steps)
+                    chunk_steps=chunk_steps, fc_min_std=getattr(cfg, "fc_min_std", 1e-9))
 
 
 class Sweep:

@@ -50,4 +50,4 @@ def test_create_without_device_fails_cleanly():
     h = C.c_void_p()
     s = vadx.lib().vadx_create(0, None, C.byref(h))
     assert s in (vadx.VADX_E_HIP, vadx.VADX_E_ARG)
-    assert vadx.lib().vadx_last_error(None) == b"null context"
+    assert vadx.lib().vadx_last_error(None).startswith(b"hipGetDeviceCount")

@@ -217,6 +217,28 @@ def test_sync_index_limits(oracle):
     assert flags & 4 and np.all(np.delete(fc[2], 2) == 0) and fc[2, 2] == 1.0
 
 
+def test_silent_regions(oracle):
+    """A region whose rate std is below the silence threshold counts as
+    zero-variance; the other regions keep numpy's correlations."""
+    rng = np.random.default_rng(13)
+    n, ns = 10, 3000
+    x = 0.004 + 1e-4 * rng.standard_normal((ns, n))
+    x[:, 3] = 4e-11 + 1e-12 * rng.standard_normal(ns)       # std 1e-12 kHz: silent
+    w = inputs.synthetic_connectome(n, seed=2).weights
+    fc, st, flags = oracle.fc_stats(x, w, min_std=1e-9)
+    keep = [k for k in range(n) if k != 3]
+    np.testing.assert_allclose(fc[np.ix_(keep, keep)], np.corrcoef(x[:, keep].T), atol=1e-12)
+    assert flags & 4 and fc[3, 3] == 1.0 and np.all(np.delete(fc[3], 3) == 0)
+    fc0, _, flags0 = oracle.fc_stats(x, w, min_std=0.0)
+    np.testing.assert_allclose(fc0, np.corrcoef(x.T), atol=1e-12)
+    assert flags0 == 0
+    # the silent region adds nothing to the population variance
+    xs = x.copy()
+    xs[:, 3] = 0.0
+    chi = np.sqrt(xs.mean(1).var() / xs.var(0).mean())
+    np.testing.assert_allclose(st[5], chi, rtol=1e-9)
+
+
 def test_uncoupled_network_is_independent_nodes(oracle):
     """S = 0: every region follows the single-region stepper driven by its own
     Philox normal stream; no coupling leaks through."""
