@@ -37,6 +37,11 @@ def parse():
     p.add_argument("--cpu-sample-steps", type=int, default=10000)
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_uniform.json"),
                    help="HBM bytes per launch measured with rocprofv3 counters, if present")
+    p.add_argument("--run-steps", type=int, default=0,
+                   help="profiling only: shorten each run to this many steps (not a bench line)")
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="profiling only: first copy a buffer of this many MiB with torch (a "
+                        "kernel of known traffic to scale FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
 
 
@@ -89,6 +94,18 @@ def main():
     from paper_2311_13337_amd import vadx
 
     conn, batch, cfg, desc = workload(args.workload)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.run_steps > 0:
+        import dataclasses
+        cfg = dataclasses.replace(cfg, n_steps=args.run_steps,
+                                  transient_steps=min(cfg.transient_steps, args.run_steps // 2))
+        desc = f"[profiling run, {args.run_steps} steps] " + desc
     sw = vadx.Sweep(0)
     sw.add_connectome(conn)
     sw.set_batch(batch)

@@ -173,6 +173,15 @@ vadx_status vadx_read_trace(vadx_ctx *ctx, int64_t slot, float *out, int32_t whe
 vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,
                                 int64_t *n_samples);
 
+/* Launch shape of the integration (takes effect at the next vadx_plan).
+ * mode 0 (default): a persistent kernel whose workgroups pull (group of
+ * instances, chunk of item_steps steps) items from a queue, chunks of one group
+ * in order, so uneven batches and grids larger than the GPU stay balanced;
+ * mode 1: one workgroup per group for each launch. wg_instances caps the
+ * instances per workgroup (0 = as many as fit 512 lanes); item_steps 0 = 1000.
+ * Results do not depend on the shape. */
+vadx_status vadx_set_launch(vadx_ctx *ctx, int32_t mode, int32_t wg_instances, int32_t item_steps);
+
 /* Kernel timing: when enabled, HIP events on the context's stream bracket every
  * launch of the integration kernel; vadx_kernel_time reports their count and
  * summed duration (ms) since the last reset, and the duration of the FC

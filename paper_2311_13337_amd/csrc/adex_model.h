@@ -180,7 +180,8 @@ template <class T> VADX_HD void erfc_and_gauss(T z, T &g, T &e)
 
 // Transfer function of population `pop` with its value and derivatives in
 // (xe, xi). Also returns mu_V (value) for the adaptation equation.
-template <class T>
+// EQ: tau_e == tau_i, so d_i = d_e, 1/tau_V = d_e and sigma_V^2 = (A_e + A_i) d_e / 2.
+template <bool EQ, class T>
 VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
 {
     const T aE = T(M.aE), aI = T(M.aI);
@@ -217,32 +218,43 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
               fmaf_(ci, Ui2.a, lxi * Ui2.ab), fmaf_(T(2) * ci, Ui2.b, lxi * Ui2.bb)};
     // d_s = 1/(C_m/G + tau_s) = G/(C_m + tau_s G): h' = C_m (d r)^2, h'' = -2 tau_s C_m (d r)^3
     T de = rcp(fmaf_(T(M.Cm), r, T(M.tau_e)));
-    T di = rcp(fmaf_(T(M.Cm), r, T(M.tau_i)));
-    T qe = de * r, qi = di * r;
-    T he1 = T(M.Cm) * qe * qe, hi1 = T(M.Cm) * qi * qi;
-    const T he2 = T(-2) * T(M.tau_e) * he1 * qe, hi2 = T(-2) * T(M.tau_i) * hi1 * qi;
+    T qe = de * r;
+    T he1 = T(M.Cm) * qe * qe;
+    const T he2 = T(-2) * T(M.tau_e) * he1 * qe;
     Jet<T> De = jofG(de, he1, he2, aE, aI);
-    Jet<T> Di = jofG(di, hi1, hi2, aE, aI);
-    Jet<T> S2 = jadd(jmul(Ae, De), jmul(Ai, Di));   // 2 sigma_V^2
     Jet<T> As = jadd(Ae, Ai);
+    Jet<T> S2, ITV, TV;                              // 2 sigma_V^2, 1/tau_V, tau_V
+    if constexpr (EQ) {
+        S2 = jmul(As, De);
+        ITV = De;
+        // tau_V = T_eff + tau_e = C_m/G + tau_e
+        TV = jofG(fmaf_(T(M.Cm), r, T(M.tau_e)), -T(M.Cm) * r2, T(2) * T(M.Cm) * r2 * r, aE, aI);
+    } else {
+        T di = rcp(fmaf_(T(M.Cm), r, T(M.tau_i)));
+        T qi = di * r;
+        T hi1 = T(M.Cm) * qi * qi;
+        const T hi2 = T(-2) * T(M.tau_i) * hi1 * qi;
+        Jet<T> Di = jofG(di, hi1, hi2, aE, aI);
+        S2 = jadd(jmul(Ae, De), jmul(Ai, Di));
+        // 1/tau_V = (A_e d_e + A_i d_i)/(A_e + A_i) = d_e + w (d_i - d_e) with
+        // w = A_i/(A_e + A_i): a weighted mean of d_e, d_i whose derivatives do
+        // not cancel when one source dominates (the ratio form loses them in FP32).
+        T ra = rcp(As.v);
+        T ra2 = ra * ra;
+        Jet<T> RA = jchain(As, ra, -ra2, T(2) * ra2 * ra);
+        Jet<T> Wi = jmul(Ai, RA);
+        Jet<T> Dd = jofG(di - de, hi1 - he1, hi2 - he2, aE, aI);
+        ITV = jadd(De, jmul(Wi, Dd));
+        T itv = rcp(ITV.v);
+        T itv2 = itv * itv;
+        TV = jchain(ITV, itv, -itv2, T(2) * itv2 * itv);
+    }
     // q = S2^(-1/2) = 1/(sqrt2 sigma_V);  (x^-1/2)' = -q^3/2, '' = 3 q^5/4
     T q = rsq(S2.v);
     T q2 = q * q, q3 = q2 * q;
     Jet<T> Q = jchain(S2, q, T(-0.5f) * q3, T(0.75f) * q3 * q2);
     // sigma_V = S2 q / sqrt2
     Jet<T> SQ = jmul(S2, Q);
-    // 1/tau_V = (A_e d_e + A_i d_i)/(A_e + A_i) = d_e + w (d_i - d_e) with
-    // w = A_i/(A_e + A_i): a weighted mean of d_e, d_i whose derivatives do not
-    // cancel when one source dominates (the ratio form loses them in FP32).
-    T ra = rcp(As.v);
-    T ra2 = ra * ra;
-    Jet<T> RA = jchain(As, ra, -ra2, T(2) * ra2 * ra);
-    Jet<T> Wi = jmul(Ai, RA);
-    Jet<T> Dd = jofG(di - de, hi1 - he1, hi2 - he2, aE, aI);
-    Jet<T> ITV = jadd(De, jmul(Wi, Dd));             // 1/tau_V
-    T itv = rcp(ITV.v);
-    T itv2 = itv * itv;
-    Jet<T> TV = jchain(ITV, itv, -itv2, T(2) * itv2 * itv);
     // normalised polynomial coordinates
     Jet<T> mm = jaffine(MU, T(M.mu_s), T(M.mu_o));
     Jet<T> ss = jaffine(SQ, T(M.sg_s), T(M.sg_o));   // sg_s includes 1/sqrt2
@@ -272,7 +284,7 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
 template <class T> struct InstParams { T S, b_e, a_e; };
 
 // Drift of one region's 8 states given its coupling input c (eq. 1-4).
-template <class T>
+template <bool EQ, class T>
 VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
 {
     const T E = X[0], I = X[1], Cee = X[2], Cei = X[3], Cii = X[4];
@@ -282,8 +294,8 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
     T xe1 = maxf_(exc + T(M.cF[1][0]), T(M.x_floor));
     T xi1 = maxf_(I + T(M.cF[1][1]), T(M.x_floor));
     T muVe, muVi;
-    Jet<T> Fe = transfer(M, 0, xe0, xi0, X[5], muVe);
-    Jet<T> Fi = transfer(M, 1, xe1, xi1, X[6], muVi);
+    Jet<T> Fe = transfer<EQ>(M, 0, xe0, xi0, X[5], muVe);
+    Jet<T> Fi = transfer<EQ>(M, 1, xe1, xi1, X[6], muVi);
     const T iT = T(M.invT);
     T fe = Fe.v - E, fi = Fi.v - I;
     // eq. 1: T dnu/dt = (F - nu) + 1/2 C_ee F_ee + C_ei F_ei + 1/2 C_ii F_ii
@@ -331,13 +343,13 @@ template <class T> VADX_HD bool project(const KModel &M, T X[8])
 // in S (double), so the rounding of the state does not build up over the
 // run. gdw is the OU increment (sigma/tau_OU) sqrt(dt) z. Returns true when a
 // bound was hit.
-template <class T, class S>
+template <bool EQ, class T, class S>
 VADX_HD bool step_region(const KModel &M, int integrator, S dt, S X[8], T c, T be, T ae, S gdw)
 {
     T xf[8], f0[8], f1[8];
     S Xt[8];
     for (int q = 0; q < 8; ++q) xf[q] = T(X[q]);
-    drift(M, xf, c, be, ae, f0);
+    drift<EQ>(M, xf, c, be, ae, f0);
     if (integrator == 1) {
         for (int q = 0; q < 8; ++q) X[q] = X[q] + dt * S(f0[q]);
         X[7] = X[7] + gdw;
@@ -347,7 +359,7 @@ VADX_HD bool step_region(const KModel &M, int integrator, S dt, S X[8], T c, T b
     Xt[7] = Xt[7] + gdw;
     bool hit = project(M, Xt);
     for (int q = 0; q < 8; ++q) xf[q] = T(Xt[q]);
-    drift(M, xf, c, be, ae, f1);
+    drift<EQ>(M, xf, c, be, ae, f1);
     const S hdt = S(0.5) * dt;
     for (int q = 0; q < 8; ++q) X[q] = X[q] + hdt * (S(f0[q]) + S(f1[q]));
     X[7] = X[7] + gdw;

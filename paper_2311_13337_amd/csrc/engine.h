@@ -17,15 +17,15 @@ constexpr int kMaxBlock = 16;
 struct InstDev {
     float S, be, ae;
     int32_t n;          // regions
-    int32_t D;          // ring depth in steps (slots per region row)
+    int32_t D;          // ring depth in steps
     int32_t conn;       // connectome
     uint32_t id;        // instance index (Philox key word 1)
-    int32_t pad;
+    int32_t Dp;         // ring row stride: D + B - 1 (mirror of the first B - 1 slots)
     int64_t table_off;  // into the packed delay tables (nnz entries)
     int64_t trace_off;  // floats: [n_trace][8][n]; -1: not traced
     int64_t state_off;  // floats (8-byte aligned): [8][n] doubles, final/resume state
     int64_t acc_off;    // floats: [n] running time-average sums
-    int64_t ring_off;   // floats: [n][D] excitatory-rate history
+    int64_t ring_off;   // floats: [n][Dp] excitatory-rate history
     int64_t samp_off;   // floats: [n_samples][n]
     int64_t fc_off;     // floats: [n][n]
 };
@@ -72,6 +72,16 @@ struct IntegrateArgs {
     int32_t block;              // steps per barrier block (<= kMaxBlock)
 };
 
+// Work queue of the persistent integration kernel (in the workspace).
+struct QueueArgs {
+    int *next;                  // next item to hand out
+    int *done;                  // per group: chunks completed in this launch
+    uint32_t *status;           // bit 0: a wait timed out
+    int n_groups, n_items;
+    int64_t item_steps;
+    uint32_t max_spins;
+};
+
 struct FcArgs {
     const InstDev *inst;
     const ConnDev *conns;
@@ -89,8 +99,11 @@ hipError_t launch_conn_prepare(int n, const double *w, const double *len, int32_
 hipError_t launch_delays(int n_tables, const DelayTableDev *tables, const ConnDev *conns,
                          const int32_t *colidx, const double *edge_len, double dt,
                          int32_t *packed, int max_nnz, hipStream_t s);
+// q == nullptr: one workgroup per group over [a.n_begin, a.n_end); otherwise the
+// persistent kernel with `grid` workgroups draining the queue.
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
-                            hipStream_t s);
+                            const QueueArgs *q, int grid, hipStream_t s);
+int persistent_blocks_per_cu(int block, int block_threads);
 hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s);
 
 } // namespace vadx

@@ -109,31 +109,38 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 }
 
 // Four standard normals for steps 4q .. 4q+3 of region k: words mapped to
-// (0, 1) as (w + 1/2) 2^-32, two Box-Muller (cos, sin) pairs.
+// (0, 1) as (w + 1/2) 2^-32, two Box-Muller (cos, sin) pairs. The hardware
+// sine/cosine take their argument in revolutions, so sin(2 pi u) is one
+// instruction; log2 and sqrt are the hardware instructions as well.
 __device__ __forceinline__ void normals4(uint32_t seed, uint32_t id, uint32_t q, uint32_t k,
                                          float z[4])
 {
     uint32_t c[4] = {q, k, 0u, 0u};
     philox4x32_10(c, seed, id);
     const float s32 = 2.3283064365386963e-10f, h32 = 1.1641532182693481e-10f;
+    const float m2ln2 = -1.3862943611198906f;   // -2 ln 2
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-        float u0 = fmaf((float)c[2 * p], s32, h32);
-        float u1 = fmaf((float)c[2 * p + 1], s32, h32);
-        float rr = sqrtf(-2.0f * logf(u0));
-        float sn, cs;
-        sincospif(2.0f * u1, &sn, &cs);
-        z[2 * p] = rr * cs;
-        z[2 * p + 1] = rr * sn;
+        const float u0 = fmaf((float)c[2 * p], s32, h32);
+        const float u1 = fmaf((float)c[2 * p + 1], s32, h32);
+        const float rr = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+        z[2 * p] = rr * __builtin_amdgcn_cosf(u1);
+        z[2 * p + 1] = rr * __builtin_amdgcn_sinf(u1);
     }
 }
 
 // ------------------------------------------------------------------ integrate
-template <int B>
-__global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
+// Integrates the instances of group g over steps [n_begin, n_end). All
+// threads of the workgroup call it with the same (wave-uniform) arguments: it
+// contains workgroup barriers.
+//
+// Ring row of region j: D slots holding E_j at steps n mod D, followed by
+// B - 1 mirror slots (slot D + s repeats slot s), so the B consecutive
+// history values a block needs from one edge never wrap.
+template <int B, bool EQ>
+__device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const GroupDev g,
+                                                int64_t n_begin, int64_t n_end, float *cbuf)
 {
-    extern __shared__ float cbuf[];   // [B][blockDim.x] coupling of the block's steps
-    const GroupDev g = a.groups[blockIdx.x];
     const int tid = threadIdx.x;
     const int slot = tid / g.n;
     const int k = tid - slot * g.n;
@@ -141,7 +148,6 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
     const int nthr = blockDim.x;
 
     InstDev I;
-    ConnDev C;
     double X[8];
     float acc = 0.f;
     int row_b = 0, row_e = 0;
@@ -149,27 +155,29 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
     const int32_t *prow = nullptr;
     float *ring = nullptr;
     float *trace = nullptr;
-    int64_t tc = 0, sidx = 0;
+    int tc = 0, sidx = 0;
     uint32_t fl = 0;
+    const int tavg = (int)a.tavg_steps;
+    const int ns = (int)a.n_samples;
     if (active) {
         I = a.inst[a.perm[g.first + slot]];
-        C = a.conns[I.conn];
+        const ConnDev C = a.conns[I.conn];
         row_b = a.rowptr[C.row_off + k];
         row_e = a.rowptr[C.row_off + k + 1];
         wrow = a.weight + C.edge_off;
         prow = a.packed + I.table_off;
         ring = a.ws + I.ring_off;
         if (I.trace_off >= 0) trace = a.ws + I.trace_off;
-        tc = a.n_begin % a.tavg_steps;
-        sidx = a.n_begin / a.tavg_steps - a.transient_steps / a.tavg_steps;
-        if (a.n_begin == 0) {
+        tc = (int)(n_begin % tavg);
+        sidx = (int)(n_begin / tavg - a.transient_steps / tavg);
+        if (n_begin == 0) {
             X[0] = a.E_init;
             X[1] = a.I_init;
 #pragma unroll
             for (int q = 2; q < 8; ++q) X[q] = 0.0;
-            float *rr = ring + (int64_t)k * I.D;
+            float *rr = ring + (int64_t)k * I.Dp;
             const float e0 = (float)a.E_init;
-            for (int s = 0; s < I.D; ++s) rr[s] = e0;
+            for (int s = 0; s < I.Dp; ++s) rr[s] = e0;
         } else {
             const double *st = reinterpret_cast<const double *>(a.ws + I.state_off);
 #pragma unroll
@@ -181,66 +189,77 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 
     const float S = active ? I.S : 0.f, be = active ? I.be : 0.f, ae = active ? I.ae : 0.f;
     const int D = active ? I.D : 1;
-    int nm = active ? (int)(a.n_begin % D) : 0;   // n0 mod D
+    const int Dp = active ? I.Dp : 1;
+    int nm = active ? (int)(n_begin % D) : 0;   // n0 mod D
+    float *myrow = active ? ring + (int64_t)k * Dp : nullptr;
     float z4[4] = {0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t n0 = a.n_begin; n0 < a.n_end; n0 += B) {
-        const int nb = (int)((a.n_end - n0) < B ? (a.n_end - n0) : B);
+    for (int64_t n0 = n_begin; n0 < n_end; n0 += B) {
+        const int nb = (int)((n_end - n0) < B ? (n_end - n0) : B);
         if (active) {
-            // coupling of steps n0 .. n0+nb-1: S sum_j W_kj H_j[n - d_kj]
+            // coupling of steps n0 .. n0+nb-1: S sum_j W_kj H_j[n - d_kj], in the
+            // fixed (ascending j) order of the CSR row
             float cb[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) cb[b] = 0.f;
-            for (int e = row_b; e < row_e; ++e) {
-                const int32_t pk = prow[e];
-                const int j = pk >> 20, d = pk & 0xFFFFF;
-                const float w = wrow[e];
-                const float *hr = ring + (int64_t)j * D;
-                int s0 = nm - d;
-                s0 += (s0 < 0) ? D : 0;
+            if (nb == B) {
+                for (int e = row_b; e < row_e; ++e) {
+                    const int32_t pk = prow[e];
+                    const int j = pk >> 20, d = pk & 0xFFFFF;
+                    const float w = wrow[e];
+                    int s0 = nm - d;
+                    s0 += (s0 < 0) ? D : 0;
+                    const float *h = ring + (int64_t)j * Dp + s0;
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    if (b < nb) {
-                        int sl = s0 + b;
-                        sl -= (sl >= D) ? D : 0;
-                        cb[b] = fmaf(w, hr[sl], cb[b]);
-                    }
+                    for (int b = 0; b < B; ++b) cb[b] = fmaf(w, h[b], cb[b]);
+                }
+            } else {
+                for (int e = row_b; e < row_e; ++e) {
+                    const int32_t pk = prow[e];
+                    const int j = pk >> 20, d = pk & 0xFFFFF;
+                    const float w = wrow[e];
+                    int s0 = nm - d;
+                    s0 += (s0 < 0) ? D : 0;
+                    const float *h = ring + (int64_t)j * Dp + s0;
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+                        if (b < nb) cb[b] = fmaf(w, h[b], cb[b]);
                 }
             }
 #pragma unroll
             for (int b = 0; b < B; ++b) cbuf[b * nthr + tid] = S * cb[b];
 
-            float *myrow = ring + (int64_t)k * D;
             int wm = nm;
+            const bool tracing = trace != nullptr && n0 < a.n_trace_steps;
             for (int b = 0; b < nb; ++b) {
-                const int64_t n = n0 + b;
-                const int r = (int)(n & 3);
+                const int n = (int)(n0 + b);
+                const int r = n & 3;
                 if (r == 0 || b == 0)
                     normals4(a.seed, I.id, (uint32_t)(n >> 2), (uint32_t)k, z4);
                 const float z = r == 0 ? z4[0] : (r == 1 ? z4[1] : (r == 2 ? z4[2] : z4[3]));
                 const float c = cbuf[b * nthr + tid];
-                bool hit = step_region(a.M, a.integrator, a.dt, X, c, be, ae,
-                                       a.gdw_scale * (double)z);
+                bool hit = step_region<EQ>(a.M, a.integrator, a.dt, X, c, be, ae,
+                                           a.gdw_scale * (double)z);
                 double chk = ((X[0] + X[1]) + (X[2] + X[3])) + ((X[4] + X[5]) + (X[6] + X[7]));
                 fl |= hit ? 2u : 0u;
                 fl |= __builtin_isfinite(chk) ? 0u : 1u;
-                // history of E: slot (n + 1) mod D
+                // history of E: slot (n + 1) mod D, and its mirror
                 wm += 1;
                 wm -= (wm >= D) ? D : 0;
                 const float e1 = (float)X[0];
                 myrow[wm] = e1;
+                if (wm < B - 1) myrow[D + wm] = e1;
                 // time average
                 acc += e1;
-                tc += 1;
-                if (tc == a.tavg_steps) {
-                    if (sidx >= 0 && sidx < a.n_samples)
-                        a.ws[I.samp_off + sidx * I.n + k] = acc / (float)a.tavg_steps;
+                if (++tc == tavg) {
+                    if (sidx >= 0 && sidx < ns)
+                        a.ws[I.samp_off + (int64_t)sidx * I.n + k] = acc / (float)tavg;
                     acc = 0.f;
                     tc = 0;
                     ++sidx;
                 }
-                if (trace != nullptr && n < a.n_trace_steps) {
-                    float *tr = trace + n * 8 * I.n + k;
+                if (tracing && n < a.n_trace_steps) {
+                    float *tr = trace + (int64_t)n * 8 * I.n + k;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) tr[q * I.n] = (float)X[q];
                 }
@@ -259,23 +278,136 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
     }
 }
 
-template <int B> static hipError_t launch_integrate_b(const IntegrateArgs &a, int n_groups,
-                                                    int block_threads, hipStream_t s)
+template <int B, bool EQ>
+__global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
+{
+    extern __shared__ float cbuf[];   // [B][blockDim.x] coupling of the block's steps
+    integrate_group<B, EQ>(a, a.groups[blockIdx.x], a.n_begin, a.n_end, cbuf);
+}
+
+// Persistent form: workgroups pull (group, chunk) items from a queue in
+// chunk-major order; chunk c of a group starts only after chunk c-1 of the
+// same group has been published (its state and history written back to
+// memory), so the groups advance in step while every workgroup stays busy
+// until the queue is empty. The wait is bounded: on timeout the kernel
+// records an error and the workgroup stops.
+template <int B, bool EQ>
+__global__ __launch_bounds__(512) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
+{
+    extern __shared__ float cbuf[];
+    __shared__ int s_item;
+    __shared__ int s_abort;
+    const int tid = threadIdx.x;
+    const int G = q.n_groups;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(q.next, 1);
+        __syncthreads();
+        // Every value that steers loops and barriers below is made wave-uniform
+        // (scalar): with an LDS-loaded index the compiler treats the loop exits
+        // as divergent and may restructure the loop so that waves reach the
+        // workgroup barriers in different orders.
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();                           // s_item read by all before it is rewritten
+        if (item >= q.n_items) break;
+        const int c = item / G, gi = item - c * G;
+        if (c > 0) {
+            if (tid == 0) {
+                uint32_t spins = 0;
+                int abort = 0;
+                while (__hip_atomic_load(&q.done[gi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < c) {
+                    __builtin_amdgcn_s_sleep(32);
+                    if (++spins > q.max_spins) {
+                        atomicOr(q.status, 1u);
+                        abort = 1;
+                        break;
+                    }
+                }
+                s_abort = abort;
+            }
+            __syncthreads();
+            const int abort = __builtin_amdgcn_readfirstlane(s_abort);
+            if (abort) break;
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);   // see the previous chunk's writes
+        }
+        const int64_t nb = a.n_begin + (int64_t)c * q.item_steps;
+        const int64_t ne = nb + q.item_steps < a.n_end ? nb + q.item_steps : a.n_end;
+        integrate_group<B, EQ>(a, a.groups[gi], nb, ne, cbuf);
+        __threadfence();                           // publish state and history
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(&q.done[gi], c + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void queue_reset_kernel(QueueArgs q)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *q.next = 0;
+    if (i < q.n_groups) q.done[i] = 0;
+}
+
+template <int B, bool EQ>
+static hipError_t launch_integrate_b(const IntegrateArgs &a, int n_groups, int block_threads,
+                                     const QueueArgs *q, int grid, hipStream_t s)
 {
     size_t lds = (size_t)B * block_threads * sizeof(float);
-    hipLaunchKernelGGL(integrate_kernel<B>, dim3(n_groups), dim3(block_threads), lds, s, a);
+    if (q == nullptr) {
+        hipLaunchKernelGGL((integrate_kernel<B, EQ>), dim3(n_groups), dim3(block_threads), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(queue_reset_kernel, dim3((q->n_groups + 255) / 256), dim3(256), 0, s, *q);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((integrate_persistent_kernel<B, EQ>), dim3(grid), dim3(block_threads),
+                           lds, s, a, *q);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads, hipStream_t s)
+template <bool EQ>
+static hipError_t launch_integrate_eq(const IntegrateArgs &a, int n_groups, int block_threads,
+                                      const QueueArgs *q, int grid, hipStream_t s)
 {
     switch (a.block) {
-    case 1: return launch_integrate_b<1>(a, n_groups, block_threads, s);
-    case 2: return launch_integrate_b<2>(a, n_groups, block_threads, s);
-    case 4: return launch_integrate_b<4>(a, n_groups, block_threads, s);
-    case 8: return launch_integrate_b<8>(a, n_groups, block_threads, s);
-    case 16: return launch_integrate_b<16>(a, n_groups, block_threads, s);
+    case 1: return launch_integrate_b<1, EQ>(a, n_groups, block_threads, q, grid, s);
+    case 2: return launch_integrate_b<2, EQ>(a, n_groups, block_threads, q, grid, s);
+    case 4: return launch_integrate_b<4, EQ>(a, n_groups, block_threads, q, grid, s);
+    case 8: return launch_integrate_b<8, EQ>(a, n_groups, block_threads, q, grid, s);
+    case 16: return launch_integrate_b<16, EQ>(a, n_groups, block_threads, q, grid, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
+                            const QueueArgs *q, int grid, hipStream_t s)
+{
+    if (a.M.tau_e == a.M.tau_i) return launch_integrate_eq<true>(a, n_groups, block_threads, q, grid, s);
+    return launch_integrate_eq<false>(a, n_groups, block_threads, q, grid, s);
+}
+
+template <int B> static int resident_b(int block_threads)
+{
+    // both model variants have the same launch bounds and LDS use
+    int per_cu = 0;
+    size_t lds = (size_t)B * block_threads * sizeof(float);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_persistent_kernel<B, true>,
+                                                     block_threads, lds) != hipSuccess)
+        return 0;
+    int per_cu2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, integrate_persistent_kernel<B, false>,
+                                                     block_threads, lds) != hipSuccess)
+        return 0;
+    return per_cu < per_cu2 ? per_cu : per_cu2;
+}
+
+int persistent_blocks_per_cu(int block, int block_threads)
+{
+    switch (block) {
+    case 1: return resident_b<1>(block_threads);
+    case 2: return resident_b<2>(block_threads);
+    case 4: return resident_b<4>(block_threads);
+    case 8: return resident_b<8>(block_threads);
+    case 16: return resident_b<16>(block_threads);
+    default: return 0;
     }
 }
 

@@ -83,7 +83,7 @@ struct vadx_ctx {
     int64_t packed_total = 0;
     int64_t n_samples = 0;
     size_t ws_bytes = 0;
-    size_t off_stats = 0, off_flags = 0;
+    size_t off_stats = 0, off_flags = 0, off_queue = 0;
     DevBuf<InstDev> d_inst;
     DevBuf<int32_t> d_perm;
     DevBuf<GroupDev> d_groups;
@@ -97,8 +97,11 @@ struct vadx_ctx {
     int64_t n_int = 0, n_fc = 0;
     double ms_int = 0.0, ms_fc = 0.0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_int, ev_fc;
-    int max_groups_per_launch = 0;   // 0: all groups
+    // launch shape: 0 = persistent work queue (default), 1 = one workgroup per group
+    int launch_mode = 0;
     int wg_instances_override = 0;
+    int item_steps = 1000;
+    int cus = 0;
 };
 
 // Errors of calls made without a context (vadx_create) land here.
@@ -165,8 +168,12 @@ vadx_status vadx_create(int device, void *hip_stream, vadx_ctx **out)
     if (device < 0 || device >= ndev) return fail(nullptr, VADX_E_ARG, "device %d out of range", device);
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, VADX_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess || cus <= 0) return fail(nullptr, VADX_E_HIP, "CU count: %s", hipGetErrorString(e));
     vadx_ctx *c = new vadx_ctx();
     c->device = device;
+    c->cus = cus;
     c->stream = (hipStream_t)hip_stream;
     vadx_model_defaults(VADX_PRESET_LITERATURE_B, &c->model);
     c->have_model = true;
@@ -437,13 +444,14 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         d.S = c->S[i]; d.be = c->be[i]; d.ae = c->ae[i];
         d.n = hc.n;
         d.D = (int32_t)(dmax[i] + B + 1);
+        d.Dp = d.D + B - 1;
         d.conn = c->conn_of[i];
         d.id = (uint32_t)i;
         d.table_off = c->h_tables[tab_of[i]].off;
         d.trace_off = -1;
         d.state_off = f_state; f_state += 16LL * hc.n;   // 8 doubles per region
         d.acc_off = f_acc; f_acc += hc.n;
-        d.ring_off = f_ring; f_ring += (int64_t)hc.n * d.D;
+        d.ring_off = f_ring; f_ring += (int64_t)hc.n * d.Dp;
         d.samp_off = f_samp; f_samp += (ns > 0 ? ns : 0) * hc.n;
         d.fc_off = f_fc; f_fc += (int64_t)hc.n * hc.n;
     }
@@ -459,6 +467,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     const size_t o_samp = section(f_samp), o_fc = section(f_fc), o_trace = section(f_trace);
     c->off_stats = off; off = align_up(off + (size_t)ni * sizeof(vadx_stats), 256);
     c->off_flags = off; off = align_up(off + (size_t)ni * 4, 256);
+    c->off_queue = off; off = align_up(off + (size_t)(c->h_groups.size() + 2) * 4, 256);
     for (auto &d : c->h_inst) {
         d.state_off += o_state / 4; d.acc_off += o_acc / 4; d.ring_off += o_ring / 4;
         d.samp_off += o_samp / 4; d.fc_off += o_fc / 4;
@@ -566,12 +575,32 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
     int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps : 10000;
     chunk = std::max<int64_t>(chunk / c->block, 1) * c->block;
     const int ng = (int)c->h_groups.size();
+    QueueArgs q{};
+    int grid = ng;
+    if (c->launch_mode == 0) {
+        int *qb = (int *)((char *)ws + c->off_queue);
+        q.next = qb;
+        q.status = (uint32_t *)(qb + 1);
+        q.done = qb + 2;
+        q.n_groups = ng;
+        q.item_steps = std::max<int64_t>(c->item_steps / c->block, 1) * c->block;
+        q.max_spins = 1u << 26;
+        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads);
+        if (per_cu <= 0) return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", c->wg_threads);
+        grid = std::min(ng, per_cu * c->cus);
+        HIP_TRY(c, hipMemsetAsync(q.status, 0, 4, c->stream));
+    }
     for (int64_t n0 = 0; n0 < r->n_steps; n0 += chunk) {
         a.n_begin = n0;
         a.n_end = std::min<int64_t>(r->n_steps, n0 + chunk);
         hipEvent_t stop = nullptr;
         if (c->timing) { vadx_status st = record(c, c->ev_int, &stop); if (st) return st; }
-        HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, c->stream));
+        if (c->launch_mode == 0) {
+            q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
+            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, &q, grid, c->stream));
+        } else {
+            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, nullptr, ng, c->stream));
+        }
         if (c->timing) HIP_TRY(c, hipEventRecord(stop, c->stream));
     }
     if (r->n_steps == 0) {
@@ -600,6 +629,23 @@ vadx_status vadx_sync(vadx_ctx *c)
     if (!c) return VADX_E_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->ran && c->launch_mode == 0) {
+        uint32_t status = 0;
+        HIP_TRY(c, hipMemcpy(&status, (char *)c->ws + c->off_queue + 4, 4, hipMemcpyDeviceToHost));
+        if (status) return fail(c, VADX_E_HIP, "integration scheduler: a wait for a previous chunk timed out");
+    }
+    return VADX_OK;
+}
+
+vadx_status vadx_set_launch(vadx_ctx *c, int32_t mode, int32_t wg_instances, int32_t item_steps)
+{
+    if (!c) return VADX_E_ARG;
+    if ((mode != 0 && mode != 1) || wg_instances < 0 || item_steps < 0)
+        return fail(c, VADX_E_ARG, "bad launch shape");
+    c->launch_mode = mode;
+    c->wg_instances_override = wg_instances;
+    c->item_steps = item_steps > 0 ? item_steps : 1000;
+    c->planned = false;
     return VADX_OK;
 }
 

@@ -140,6 +140,22 @@ def grid_4d(res: int = 32) -> Batch:
     return _batch(G[:, 0], G[:, 1], G[:, 2], G[:, 3])
 
 
+MLP_SHAPES = (("W1", (128, 4)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+              ("W3", (6, 128)), ("b3", (6,)))
+
+
+def mlp_init_params(seed: int = 0) -> np.ndarray:
+    """Initial surrogate parameters (W1, b1, W2, b2, W3, b3 concatenated,
+    row-major), each uniform in +-1/sqrt(fan_in), as float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in MLP_SHAPES:
+        fan_in = {"W1": 4, "b1": 4, "W2": 128, "b2": 128, "W3": 128, "b3": 128}[name]
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, shape).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
 @dataclasses.dataclass
 class RunConfig:
     """Time axis of one sweep run. Steps of dt ms; a rate sample is the mean of

@@ -27,7 +27,8 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_set_model", "vadx_add_connectome", "vadx_set_batch", "vadx_set_trace",
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
-           "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops")
+           "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
+           "vadx_set_launch")
 
 
 class VadxError(RuntimeError):
@@ -93,6 +94,7 @@ def lib():
             "vadx_read_trace": (st, [vp, C.c_int64, vp, C.c_int32]),
             "vadx_instance_shape": (st, [vp, C.c_int64, P(C.c_int32), P(C.c_int64)]),
             "vadx_enable_timing": (st, [vp, C.c_int32]),
+            "vadx_set_launch": (st, [vp, C.c_int32, C.c_int32, C.c_int32]),
             "vadx_kernel_time": (st, [vp, P(C.c_int64), P(C.c_double), P(C.c_int64),
                                       P(C.c_double)]),
             "vadx_region_step_ops": (st, [C.c_int32, P(C.c_double), P(C.c_double),
@@ -222,6 +224,9 @@ class Context:
     def vadx_read_trace(self, slot: int, inst: int, n_trace_steps: int) -> np.ndarray:
         n, _ = self.vadx_instance_shape(inst)
         return self._read("vadx_read_trace", slot, (n_trace_steps, 8, n))
+
+    def vadx_set_launch(self, mode: int = 0, wg_instances: int = 0, item_steps: int = 0):
+        self._check(lib().vadx_set_launch(self.h, mode, wg_instances, item_steps))
 
     def vadx_enable_timing(self, on: bool = True):
         self._check(lib().vadx_enable_timing(self.h, 1 if on else 0))

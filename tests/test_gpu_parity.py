@@ -223,6 +223,29 @@ def test_euler_and_noise_free(oracle, integrator, noise_off):
                     f"noise_off {noise_off} instance {i}", require_full=True)
 
 
+def test_launch_shapes_are_bit_identical():
+    """Persistent queue vs one workgroup per group, different instances per
+    workgroup and chunk lengths: identical bits (the arithmetic of a lane does
+    not depend on how instances are grouped or scheduled)."""
+    conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
+    b = inputs.grid_uneven(30, seed=9)
+    cfg = inputs.RunConfig(n_steps=700, transient_steps=100, seed=2)
+    outs = []
+    for mode, wg, item in ((1, 0, 0), (0, 0, 0), (0, 3, 96), (0, 1, 250)):
+        sw = vadx.Sweep(0, gpu_model("literature-B"))
+        ids = [sw.add_connectome(c) for c in conns]
+        sw.ctx.vadx_set_launch(mode, wg, item)
+        sw.set_batch(b, conn_ids=ids)
+        sw.plan(vadx.make_run(cfg))
+        sw.integrate()
+        sw.sync()
+        outs.append(([sw.ctx.vadx_read_state(i) for i in range(len(b))],
+                     [sw.ctx.vadx_read_fc(i) for i in range(len(b))]))
+    for o in outs[1:]:
+        for i in range(len(b)):
+            assert np.array_equal(o[0][i], outs[0][0][i]) and np.array_equal(o[1][i], outs[0][1][i])
+
+
 def test_chunked_launches_are_bit_identical():
     conn = inputs.synthetic_connectome(68)
     batch = inputs.grid_small()
