@@ -190,6 +190,55 @@ vadx_status vadx_enable_timing(vadx_ctx *ctx, int32_t on);
 vadx_status vadx_kernel_time(vadx_ctx *ctx, int64_t *n_integrate_launches, double *integrate_ms,
                              int64_t *n_fc_launches, double *fc_ms);
 
+/* ---------------------------------------------------------------------------
+ * Surrogate network: a 4 -> 128 -> 128 -> 6 MLP with GELU (exact erf form)
+ * mapping a sweep point (S, b_e, a_e, v) to the six statistics of
+ * vadx_read_stats, trained on the GPU by this library's kernels so a dense grid
+ * can be screened before simulating (the learning-guided exploration the
+ * paper's discussion proposes; the plain simulation stays the judge).
+ * Inputs are min-max scaled to [-1, 1] with cfg.x_lo / x_hi; targets are
+ * z-scored with the network's target normalisation. Matrix products use
+ * bfloat16 operands with FP32 accumulation (MFMA for the 128 x 128 products);
+ * Adam (Kingma & Ba) in FP32. Parameter vector (17926 floats): W1 [128][4],
+ * b1 [128], W2 [128][128], b2 [128], W3 [6][128], b3 [6], row-major,
+ * concatenated. Data pointers X [n][4] and Y [n][6] are device arrays (FP32);
+ * calls are ordered on cfg.hip_stream. */
+typedef struct vadx_mlp vadx_mlp;
+typedef struct vadx_mlp_cfg {
+    float x_lo[4], x_hi[4];
+    float lr, beta1, beta2, eps;
+    void *hip_stream;
+} vadx_mlp_cfg;
+
+/* init_params: host array of 17926 floats (copied). */
+vadx_status vadx_mlp_create(vadx_ctx *ctx, const vadx_mlp_cfg *cfg, const float *init_params,
+                            vadx_mlp **out);
+void vadx_mlp_destroy(vadx_mlp *mlp);
+const char *vadx_mlp_last_error(const vadx_mlp *mlp);
+/* Target normalisation: fit = mean and population std of each column of the
+ * device array Y [n][6] (computed on the device); get/set use host arrays. */
+vadx_status vadx_mlp_fit_target_norm(vadx_mlp *mlp, const float *Y, int64_t n);
+vadx_status vadx_mlp_get_target_norm(vadx_mlp *mlp, float *mean, float *std_);
+vadx_status vadx_mlp_set_target_norm(vadx_mlp *mlp, const float *mean, const float *std_);
+/* Host copies of the 17926 parameters. */
+vadx_status vadx_mlp_get_params(vadx_mlp *mlp, float *out);
+vadx_status vadx_mlp_set_params(vadx_mlp *mlp, const float *params);
+/* Mean squared error over the n samples and the 6 normalised outputs, and its
+ * gradient (host, 17926 floats), without updating the parameters. */
+vadx_status vadx_mlp_grad(vadx_mlp *mlp, const float *X, const float *Y, int64_t n, float *grad,
+                          float *loss);
+/* epochs passes over the n samples in order, in minibatches of `batch`, one
+ * Adam step per minibatch; loss_hist (host, `epochs` floats) receives each
+ * epoch's mean training loss. */
+vadx_status vadx_mlp_train(vadx_mlp *mlp, const float *X, const float *Y, int64_t n,
+                           int32_t epochs, int32_t batch, float *loss_hist);
+/* Forward pass over n points: Y [n][6] in target units; J (nullable) [n][6][4]
+ * = d(normalised output)/d(normalised input); score (nullable) [n] =
+ * Euclidean norm of the input gradients of outputs score_out0 and score_out1
+ * (the transition score used to pick points to simulate). Device arrays. */
+vadx_status vadx_mlp_predict(vadx_mlp *mlp, const float *X, int64_t n, float *Y, float *J,
+                             float *score, int32_t score_out0, int32_t score_out1);
+
 /* Arithmetic of one region-step in this library's formulation, counted by
  * running the kernel's own model code with an operation-counting scalar:
  * single- and double-precision FLOPs (add, mul = 1, fma = 2, transcendental =

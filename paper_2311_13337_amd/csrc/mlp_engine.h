@@ -1,0 +1,30 @@
+// mlp_engine.h -- device layout and launchers of the surrogate network
+// (internal to libvadx).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vadx {
+
+constexpr int kMlpTile = 32;            // samples per workgroup
+constexpr int kMlpParams = 17926;       // W1 128x4, b1 128, W2 128x128, b2 128, W3 6x128, b3 6
+constexpr int kMlpOffW1 = 0, kMlpOffB1 = 512, kMlpOffW2 = 640, kMlpOffB2 = 17024;
+constexpr int kMlpOffW3 = 17152, kMlpOffB3 = 17920, kMlpOffLoss = 17926;
+constexpr int kMlpSlot = 17984;         // per-tile gradient slot (params + loss, padded)
+
+struct MlpArgs {
+    float *params, *m, *v, *grad, *partial, *loss_out;
+    float x_lo[4], x_scale[4];          // x_n = (x - lo) * scale - 1, scale = 2 / (hi - lo)
+    float y_mean[6], y_rstd[6], y_std[6];
+    float lr, beta1, beta2, eps;
+    int score_out0, score_out1;         // outputs whose input gradients form the score
+};
+
+hipError_t launch_mlp_grad(const MlpArgs &a, const float *X, const float *Y, int n, int n_total,
+                           hipStream_t s);
+hipError_t launch_mlp_adam(const MlpArgs &a, int n_tiles, float c1, float c2, int apply, int step,
+                           hipStream_t s);
+hipError_t launch_mlp_predict(const MlpArgs &a, const float *X, int64_t n, float *Y, float *J,
+                              float *score, hipStream_t s);
+
+} // namespace vadx

@@ -28,7 +28,11 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
            "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
-           "vadx_set_launch")
+           "vadx_set_launch", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
+           "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
+           "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
+           "vadx_mlp_predict")
+MLP_PARAMS = 17926
 
 
 class VadxError(RuntimeError):
@@ -51,6 +55,12 @@ class vadx_run(C.Structure):
                 ("tavg_steps", C.c_int64), ("n_trace_steps", C.c_int64), ("seed", C.c_uint32),
                 ("integrator", C.c_int32), ("noise_off", C.c_int32), ("chunk_steps", C.c_int32),
                 ("fc_min_std", C.c_double)]
+
+
+class vadx_mlp_cfg(C.Structure):
+    _fields_ = [("x_lo", C.c_float * 4), ("x_hi", C.c_float * 4), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("hip_stream", C.c_void_p)]
 
 
 class vadx_stats(C.Structure):
@@ -99,6 +109,17 @@ def lib():
                                       P(C.c_double)]),
             "vadx_region_step_ops": (st, [C.c_int32, P(C.c_double), P(C.c_double),
                                           P(C.c_double)]),
+            "vadx_mlp_create": (st, [vp, P(vadx_mlp_cfg), vp, P(vp)]),
+            "vadx_mlp_destroy": (None, [vp]),
+            "vadx_mlp_last_error": (C.c_char_p, [vp]),
+            "vadx_mlp_fit_target_norm": (st, [vp, vp, C.c_int64]),
+            "vadx_mlp_get_target_norm": (st, [vp, vp, vp]),
+            "vadx_mlp_set_target_norm": (st, [vp, vp, vp]),
+            "vadx_mlp_get_params": (st, [vp, vp]),
+            "vadx_mlp_set_params": (st, [vp, vp]),
+            "vadx_mlp_grad": (st, [vp, vp, vp, C.c_int64, vp, P(C.c_float)]),
+            "vadx_mlp_train": (st, [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, vp]),
+            "vadx_mlp_predict": (st, [vp, vp, C.c_int64, vp, vp, vp, C.c_int32, C.c_int32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -298,3 +319,96 @@ class Sweep:
     @property
     def n_inst(self):
         return len(self.ctx._keep[0][0])
+
+
+class Mlp:
+    """The surrogate network (vadx_mlp_*). Device data are torch CUDA float32
+    tensors; their pointers are passed through unchanged."""
+
+    def __init__(self, init_params, x_lo, x_hi, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 stream=None, device: int = 0):
+        import torch
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        cfg = vadx_mlp_cfg()
+        cfg.x_lo[:] = [float(v) for v in x_lo]
+        cfg.x_hi[:] = [float(v) for v in x_hi]
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, betas[0], betas[1], eps
+        cfg.hip_stream = C.c_void_p(stream.cuda_stream)
+        p = np.ascontiguousarray(init_params, np.float32)
+        assert p.size == MLP_PARAMS
+        h = C.c_void_p()
+        s = lib().vadx_mlp_create(None, C.byref(cfg), _ptr(p), C.byref(h))
+        if s != VADX_OK:
+            raise VadxError(s, "vadx_mlp_create")
+        self.h = h
+
+    def _check(self, s):
+        if s != VADX_OK:
+            raise VadxError(s, (lib().vadx_mlp_last_error(self.h) or b"").decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vadx_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _dptr(t, cols):
+        assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous() and t.shape[-1] == cols
+        return C.c_void_p(t.data_ptr())
+
+    def fit_target_norm(self, Y):
+        self._check(lib().vadx_mlp_fit_target_norm(self.h, self._dptr(Y, 6), Y.shape[0]))
+
+    def target_norm(self):
+        m, sd = np.zeros(6, np.float32), np.zeros(6, np.float32)
+        self._check(lib().vadx_mlp_get_target_norm(self.h, _ptr(m), _ptr(sd)))
+        return m, sd
+
+    def set_target_norm(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float32)
+        sd = np.ascontiguousarray(std, np.float32)
+        self._check(lib().vadx_mlp_set_target_norm(self.h, _ptr(m), _ptr(sd)))
+
+    def params(self):
+        out = np.zeros(MLP_PARAMS, np.float32)
+        self._check(lib().vadx_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self._check(lib().vadx_mlp_set_params(self.h, _ptr(p)))
+
+    def grad(self, X, Y):
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = C.c_float()
+        self._check(lib().vadx_mlp_grad(self.h, self._dptr(X, 4), self._dptr(Y, 6), X.shape[0],
+                                        _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train(self, X, Y, epochs, batch):
+        hist = np.zeros(max(epochs, 1), np.float32)
+        self._check(lib().vadx_mlp_train(self.h, self._dptr(X, 4), self._dptr(Y, 6), X.shape[0],
+                                         epochs, batch, _ptr(hist)))
+        return hist[:epochs]
+
+    def predict(self, X, jacobian=False, score_outputs=None):
+        torch = self.torch
+        n = X.shape[0]
+        Y = torch.empty((n, 6), dtype=torch.float32, device=X.device)
+        J = torch.empty((n, 6, 4), dtype=torch.float32, device=X.device) if jacobian else None
+        sc = torch.empty(n, dtype=torch.float32, device=X.device) if score_outputs else None
+        o0, o1 = score_outputs if score_outputs else (0, 5)
+        self._check(lib().vadx_mlp_predict(
+            self.h, self._dptr(X, 4), n, C.c_void_p(Y.data_ptr()),
+            C.c_void_p(J.data_ptr()) if J is not None else None,
+            C.c_void_p(sc.data_ptr()) if sc is not None else None, o0, o1))
+        return Y, J, sc
