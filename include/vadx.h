@@ -129,6 +129,13 @@ vadx_status vadx_add_connectome(vadx_ctx *ctx, int32_t n, const double *weights,
 vadx_status vadx_set_batch(vadx_ctx *ctx, int64_t n_inst, const float *S, const float *b_e,
                            const float *a_e, const float *v_mps, const int32_t *conn_id);
 
+/* Sets the Philox key word of each instance of the current batch (n must equal
+ * the batch size; host array, copied). The noise of eq. (4) for instance i is
+ * drawn from the stream keyed by (run seed, keys[i]); set_batch resets the
+ * keys to the batch indices 0..n-1. Giving a sub-batch the indices its points
+ * have in a larger sweep reproduces exactly the runs of that sweep. */
+vadx_status vadx_set_noise_keys(vadx_ctx *ctx, int64_t n, const uint32_t *keys);
+
 /* Chooses up to 1024 instances whose first run->n_trace_steps states are
  * recorded (trace slot i = inst[i]). n = 0 clears the selection. */
 vadx_status vadx_set_trace(vadx_ctx *ctx, int64_t n, const int64_t *inst);

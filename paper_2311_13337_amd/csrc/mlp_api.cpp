@@ -26,6 +26,7 @@ struct vadx_mlp {
     int64_t losses_n = 0;
     int64_t step = 0;                // Adam steps taken
     double *stat = nullptr;          // target statistics scratch (12 doubles)
+    float *loss1 = nullptr;          // loss sum of one gradient evaluation
 };
 
 static vadx_status mfail(vadx_mlp *m, vadx_status st, const char *msg, hipError_t e = hipSuccess)
@@ -104,7 +105,8 @@ vadx_status vadx_mlp_create(vadx_ctx *ctx, const vadx_mlp_cfg *cfg, const float 
     m->stream = (hipStream_t)cfg->hip_stream;
     m->cfg = *cfg;
     if (hipMalloc((void **)&m->dev, sizeof(float) * 4 * kMlpParams) != hipSuccess ||
-        hipMalloc((void **)&m->stat, sizeof(double) * 12) != hipSuccess) {
+        hipMalloc((void **)&m->stat, sizeof(double) * 12) != hipSuccess ||
+        hipMalloc((void **)&m->loss1, sizeof(float)) != hipSuccess) {
         vadx_mlp_destroy(m);
         return VADX_E_OOM;
     }
@@ -147,6 +149,7 @@ void vadx_mlp_destroy(vadx_mlp *m)
     if (m->partial) (void)hipFree(m->partial);
     if (m->losses) (void)hipFree(m->losses);
     if (m->stat) (void)hipFree(m->stat);
+    if (m->loss1) (void)hipFree(m->loss1);
     delete m;
 }
 
@@ -212,18 +215,15 @@ vadx_status vadx_mlp_grad(vadx_mlp *m, const float *X, const float *Y, int64_t n
         return mfail(m, VADX_E_ARG, "bad arguments");
     const int tiles = (int)((n + kMlpTile - 1) / kMlpTile);
     MHIP(m, ensure_partial(m, tiles));
-    float *lbuf = nullptr;
-    MHIP(m, hipMalloc((void **)&lbuf, sizeof(float)));
     MlpArgs a = m->a;
-    a.loss_out = lbuf;
+    a.loss_out = m->loss1;
     hipError_t e = launch_mlp_grad(a, X, Y, (int)n, (int)n, m->stream);
     if (e == hipSuccess) e = launch_mlp_adam(a, tiles, 1.f, 1.f, 0, 0, m->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(grad_out, a.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, m->stream);
     float l = 0.f;
-    if (e == hipSuccess) e = hipMemcpyAsync(&l, lbuf, sizeof(float), hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&l, m->loss1, sizeof(float), hipMemcpyDeviceToHost, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
-    (void)hipFree(lbuf);
     if (e != hipSuccess) return mfail(m, VADX_E_HIP, "gradient", e);
     *loss_out = l / (6.0f * (float)n);
     return VADX_OK;

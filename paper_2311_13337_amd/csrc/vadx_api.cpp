@@ -69,6 +69,7 @@ struct vadx_ctx {
     // batch
     std::vector<float> S, be, ae, v;
     std::vector<int32_t> conn_of;
+    std::vector<uint32_t> noise_key;     // Philox key word per instance (default: batch index)
     std::vector<int64_t> traced;
     // plan
     bool planned = false;
@@ -328,7 +329,20 @@ vadx_status vadx_set_batch(vadx_ctx *c, int64_t n, const float *S, const float *
     c->v.assign(v, v + n);
     c->conn_of.assign((size_t)n, 0);
     if (conn) c->conn_of.assign(conn, conn + n);
+    c->noise_key.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) c->noise_key[(size_t)i] = (uint32_t)i;
     c->traced.clear();
+    c->planned = false;
+    c->ran = false;
+    return VADX_OK;
+}
+
+vadx_status vadx_set_noise_keys(vadx_ctx *c, int64_t n, const uint32_t *keys)
+{
+    if (!c) return VADX_E_ARG;
+    if (n != (int64_t)c->S.size() || (n > 0 && !keys))
+        return fail(c, VADX_E_ARG, "need one noise key per instance of the batch");
+    c->noise_key.assign(keys, keys + n);
     c->planned = false;
     c->ran = false;
     return VADX_OK;
@@ -446,7 +460,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         d.D = (int32_t)(dmax[i] + B + 1);
         d.Dp = d.D + B - 1;
         d.conn = c->conn_of[i];
-        d.id = (uint32_t)i;
+        d.id = c->noise_key[(size_t)i];
         d.table_off = c->h_tables[tab_of[i]].off;
         d.trace_off = -1;
         d.state_off = f_state; f_state += 16LL * hc.n;   // 8 doubles per region

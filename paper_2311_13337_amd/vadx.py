@@ -28,7 +28,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
            "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
-           "vadx_set_launch", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
+           "vadx_set_launch", "vadx_set_noise_keys", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict")
@@ -94,6 +94,7 @@ def lib():
             "vadx_add_connectome": (st, [vp, C.c_int32, vp, vp, P(C.c_int32)]),
             "vadx_set_batch": (st, [vp, C.c_int64, vp, vp, vp, vp, vp]),
             "vadx_set_trace": (st, [vp, C.c_int64, vp]),
+            "vadx_set_noise_keys": (st, [vp, C.c_int64, vp]),
             "vadx_plan": (st, [vp, P(vadx_run), P(C.c_size_t)]),
             "vadx_integrate": (st, [vp, P(vadx_run), vp, C.c_size_t]),
             "vadx_sync": (st, [vp]),
@@ -197,6 +198,10 @@ class Context:
         self._check(lib().vadx_set_batch(self.h, arrs[0].shape[0], *[_ptr(x) for x in arrs],
                                          None if cp is None else _ptr(cp)))
 
+    def vadx_set_noise_keys(self, keys):
+        a = np.ascontiguousarray(keys, np.uint32)
+        self._check(lib().vadx_set_noise_keys(self.h, a.shape[0], _ptr(a) if a.size else None))
+
     def vadx_set_trace(self, inst):
         a = np.ascontiguousarray(inst, np.int64)
         self._check(lib().vadx_set_trace(self.h, a.shape[0], _ptr(a) if a.size else None))
@@ -285,9 +290,11 @@ class Sweep:
     def add_connectome(self, conn) -> int:
         return self.ctx.vadx_add_connectome(conn.weights, conn.tract_mm)
 
-    def set_batch(self, batch, conn_ids=None):
+    def set_batch(self, batch, conn_ids=None, noise_keys=None):
         conn = batch.conn if conn_ids is None else np.asarray(conn_ids)[batch.conn]
         self.ctx.vadx_set_batch(batch.S, batch.b_e, batch.a_e, batch.v, conn)
+        if noise_keys is not None:
+            self.ctx.vadx_set_noise_keys(noise_keys)
 
     def plan(self, run: vadx_run, trace=()):
         self.ctx.vadx_set_trace(list(trace))

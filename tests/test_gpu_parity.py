@@ -259,6 +259,27 @@ def test_chunked_launches_are_bit_identical():
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 
 
+def test_noise_keys_reproduce_sweep_members():
+    """A sub-batch given the noise keys its points have in the full sweep
+    reproduces those runs bit for bit (refinement of a screened grid)."""
+    conn = inputs.synthetic_connectome(68)
+    batch = inputs.grid_small()
+    cfg = inputs.RunConfig(n_steps=800, transient_steps=100)
+    full = run_gpu("literature-B", [conn], batch, cfg)
+    pick = [6, 1, 3]
+    sw = vadx.Sweep(0, gpu_model("literature-B"))
+    sw.add_connectome(conn)
+    sw.set_batch(batch.subset(pick), noise_keys=pick)
+    sw.plan(vadx.make_run(cfg))
+    sw.integrate()
+    sw.sync()
+    for q, i in enumerate(pick):
+        assert np.array_equal(sw.ctx.vadx_read_state(q), full.ctx.vadx_read_state(i))
+        assert np.array_equal(sw.ctx.vadx_read_fc(q), full.ctx.vadx_read_fc(i))
+    with pytest.raises(vadx.VadxError):
+        sw.ctx.vadx_set_noise_keys([1, 2])
+
+
 def test_degenerate_runs():
     conn = inputs.synthetic_connectome(68)
     batch = inputs.grid_small().subset([0])
