@@ -246,6 +246,18 @@ vadx_status vadx_mlp_train(vadx_mlp *mlp, const float *X, const float *Y, int64_
 vadx_status vadx_mlp_predict(vadx_mlp *mlp, const float *X, int64_t n, float *Y, float *J,
                              float *score, int32_t score_out0, int32_t score_out1);
 
+/* Selection after screening a grid: of the n scores (device FP32), the k
+ * largest (ties go to the lower index) plus an audit sample of the rest, each
+ * remaining point taken independently with probability audit_frac by a
+ * Philox4x32-10 draw keyed (seed, point index). sel (device, capacity
+ * entries) receives the selected indices in ascending order; is_audit
+ * (device, nullable) marks the audit picks with 1. *n_sel (host) receives the
+ * count; VADX_E_OOM (with *n_sel set) when it exceeds capacity. Synchronises
+ * the network's stream. */
+vadx_status vadx_mlp_select(vadx_mlp *mlp, const float *score, int64_t n, int64_t k,
+                            float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
+                            int64_t capacity, int64_t *n_sel);
+
 /* Arithmetic of one region-step in this library's formulation, counted by
  * running the kernel's own model code with an operation-counting scalar:
  * single- and double-precision FLOPs (add, mul = 1, fma = 2, transcendental =

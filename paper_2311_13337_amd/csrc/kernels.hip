@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include "engine.h"
+#include "philox.h"
 
 namespace vadx {
 
@@ -90,23 +91,7 @@ hipError_t launch_delays(int n_tables, const DelayTableDev *tables, const ConnDe
 }
 
 // ------------------------------------------------------------------ noise
-// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products
-// with the round keys bumped by the Weyl constants.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
+// Philox4x32-10 is in philox.h.
 
 // Four standard normals for steps 4q .. 4q+3 of region k: words mapped to
 // (0, 1) as (w + 1/2) 2^-32, two Box-Muller (cos, sin) pairs. The hardware

@@ -27,4 +27,13 @@ hipError_t launch_mlp_adam(const MlpArgs &a, int n_tiles, float c1, float c2, in
 hipError_t launch_mlp_predict(const MlpArgs &a, const float *X, int64_t n, float *Y, float *J,
                               float *score, hipStream_t s);
 
+// screening selection (select.hip)
+int64_t select_tiles(int64_t n);
+hipError_t launch_sel_hist(const float *score, int64_t n, uint32_t prefix, uint32_t mask, int shift,
+                           uint32_t *hist, hipStream_t s);
+hipError_t launch_sel_compact(const float *score, int64_t n, int phase, int use_top, uint32_t T,
+                              int64_t need, float audit_frac, uint32_t seed, const int64_t *eq_base,
+                              const int64_t *sel_base, uint32_t *out, int64_t *sel,
+                              uint8_t *is_audit, hipStream_t s);
+
 } // namespace vadx

@@ -1,0 +1,206 @@
+"""Surrogate-guided sweep over (S, b_e, a_e, v) on one GPU.
+
+The plain method simulates every point of a dense grid. The guided sweep
+  1. simulates a training set of points drawn uniformly from the sweep box,
+  2. trains the surrogate network on their statistics (vadx_mlp_train, early
+     stopping on a held-out tenth),
+  3. screens the whole grid with the network: predicted statistics and the
+     input-gradient norm of (sync_index, fc_mean), large where the dynamics
+     change regime,
+  4. simulates the points of largest gradient plus a random audit sample,
+     each with the noise stream it has in the plain sweep (its grid index as
+     noise key), so a refined point carries exactly its plain-sweep value,
+  5. keeps the predictions elsewhere.
+The plain simulation stays the judge: the error of the guided result is
+measured against plain runs of a random sample of grid points (bit-identical
+to the full plain sweep at those points), and the plain sweep's time is the
+measured per-instance time of the same simulations times the grid size.
+
+All arithmetic runs in libvadx (simulation, training, screening, selection);
+this module moves arrays between the calls and keeps the clock.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import inputs, vadx
+
+STATS = vadx.STAT_NAMES
+BOX = [inputs.SWEEP_BOX[a] for a in ("S", "b_e", "a_e", "v")]
+TRAIN_KEY_BASE = 0x80000000          # noise keys of training runs (grid points use their index)
+CHECK_SEED = 1
+
+
+@dataclasses.dataclass
+class GuidedConfig:
+    grid_res: int = 32                 # points per axis of the grid
+    n_train: int = 32768               # training simulations
+    train_seed: int = 4
+    top_frac: float = 0.05             # refined by predicted transition gradient
+    audit_frac: float = 0.01           # random audit of the rest
+    audit_seed: int = 7
+    run: inputs.RunConfig = inputs.RUN_UNIFORM
+    batch: int = 1024
+    lr: float = 1e-3
+    max_epochs: int = 400
+    eval_every: int = 5
+    patience: int = 40                 # epochs without a better validation loss
+    val_frac: float = 0.1
+    split_seed: int = 0
+    init_seed: int = 0
+    n_check: int = 4096                # grid points simulated plainly to measure the error
+    chunk: int = 16384                 # instances per simulation launch
+    err_bound: float = 0.05
+
+
+class Simulator:
+    """One context with the 68-region connectome; runs batches in chunks."""
+
+    def __init__(self, conn, run_cfg, chunk, log=print):
+        self.sw = vadx.Sweep(0)
+        self.sw.add_connectome(conn)
+        self.run = vadx.make_run(run_cfg)
+        self.chunk = chunk
+        self.log = log
+        self.units_per_inst = conn.n * run_cfg.n_steps * run_cfg.dt_ms / 1000.0
+
+    def __call__(self, batch, keys, label):
+        n = len(batch)
+        out = np.zeros((n, len(STATS)), np.float32)
+        flags = np.zeros(n, np.uint32)
+        t0 = time.perf_counter()
+        for c0 in range(0, n, self.chunk):
+            idx = np.arange(c0, min(n, c0 + self.chunk))
+            self.sw.set_batch(batch.subset(idx), noise_keys=np.asarray(keys)[idx])
+            self.sw.plan(self.run)
+            self.sw.integrate()
+            self.sw.sync()
+            st = self.sw.stats()
+            for j, name in enumerate(STATS):
+                out[idx, j] = st[name]
+            flags[idx] = st["flags"]
+            self.log(f"[guided] {label}: {idx[-1] + 1}/{n} simulated "
+                     f"({time.perf_counter() - t0:.1f} s)")
+        return out, flags, time.perf_counter() - t0
+
+
+def _points(batch):
+    return np.stack([batch.S, batch.b_e, batch.a_e, batch.v], 1).astype(np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def train_surrogate(X, Y, cfg: GuidedConfig, log=print):
+    """Trains the network on (X, Y) host arrays; returns (net, info)."""
+    import torch
+    n = X.shape[0]
+    perm = np.random.default_rng(cfg.split_seed).permutation(n)
+    n_val = max(1, int(round(cfg.val_frac * n)))
+    va, tr = perm[:n_val], perm[n_val:]
+    Xtr, Ytr, Xva, Yva = _dev(X[tr]), _dev(Y[tr]), _dev(X[va]), _dev(Y[va])
+    lo = [b[0] for b in BOX]
+    hi = [b[1] for b in BOX]
+    net = vadx.Mlp(inputs.mlp_init_params(cfg.init_seed), lo, hi, lr=cfg.lr)
+    net.fit_target_norm(Ytr)
+    t0 = time.perf_counter()
+    best, best_p, best_ep, ep = np.inf, net.params(), 0, 0
+    history = []
+    while ep < cfg.max_epochs:
+        h = net.train(Xtr, Ytr, cfg.eval_every, cfg.batch)
+        ep += cfg.eval_every
+        val, _ = net.grad(Xva, Yva)
+        history.append((ep, float(h[-1]), float(val)))
+        if val < best:
+            best, best_p, best_ep = val, net.params(), ep
+        elif ep - best_ep >= cfg.patience:
+            break
+    net.set_params(best_p)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    log(f"[guided] trained {ep} epochs in {secs:.1f} s; best validation MSE {best:.4f} "
+        f"(normalised units) at epoch {best_ep}")
+    return net, {"epochs": ep, "best_epoch": best_ep, "val_mse": float(best), "seconds": secs,
+                 "history": history}
+
+
+def screen(net, grid_X, cfg: GuidedConfig):
+    """Predicted statistics of every grid point and the selected indices."""
+    import torch
+    t0 = time.perf_counter()
+    Xd = _dev(grid_X)
+    Y, _, score = net.predict(Xd, jacobian=False,
+                              score_outputs=(STATS.index("sync_index"), STATS.index("fc_mean")))
+    n = grid_X.shape[0]
+    k = int(round(cfg.top_frac * n))
+    cap = k + int(n * cfg.audit_frac * 1.5) + 1024
+    sel = torch.empty(cap, dtype=torch.int64, device=Xd.device)
+    aud = torch.empty(cap, dtype=torch.uint8, device=Xd.device)
+    m = net.select(score, k, cfg.audit_frac, cfg.audit_seed, sel, aud)
+    Yh = Y.cpu().numpy()
+    idx = sel[:m].cpu().numpy()
+    is_aud = aud[:m].cpu().numpy().astype(bool)
+    torch.cuda.synchronize()
+    return Yh, idx, is_aud, time.perf_counter() - t0
+
+
+def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False):
+    """Runs the guided sweep and its check against the plain method. With
+    plain_full the whole grid is also simulated plainly (small grids only)."""
+    conn = inputs.synthetic_connectome(68)
+    sim = Simulator(conn, cfg.run, cfg.chunk, log)
+    grid = inputs.grid_4d(cfg.grid_res)
+    G = _points(grid)
+    n = len(grid)
+
+    train = inputs.sample_box(cfg.n_train, seed=cfg.train_seed)
+    Ytrain, ftrain, t_data = sim(train, TRAIN_KEY_BASE + np.arange(cfg.n_train), "training set")
+    net, tinfo = train_surrogate(_points(train), Ytrain, cfg, log)
+    Yhat, idx, is_aud, t_screen = screen(net, G, cfg)
+    log(f"[guided] screened {n} points in {t_screen:.2f} s; refining {len(idx)} "
+        f"({int((~is_aud).sum())} by gradient, {int(is_aud.sum())} audit)")
+    Yref, fref, t_refine = sim(grid.subset(idx), idx, "refinement")
+    guided = Yhat.copy()
+    guided[idx] = Yref
+    refined = np.zeros(n, bool)
+    refined[idx] = True
+    t_guided = t_data + tinfo["seconds"] + t_screen + t_refine
+
+    if plain_full:
+        chk = np.arange(n)
+    else:
+        chk = np.sort(np.random.default_rng(CHECK_SEED).choice(n, min(cfg.n_check, n),
+                                                              replace=False))
+    Yplain, _, t_check = sim(grid.subset(chk), chk, "plain check")
+    sec_per_inst = (t_refine + t_check) / (len(idx) + len(chk))
+    t_plain = t_check if plain_full else sec_per_inst * n
+
+    def errs(col):
+        e = np.abs(guided[chk, col] - Yplain[:, col])
+        e_pred = np.abs(Yhat[chk, col] - Yplain[:, col])
+        return {"p95": float(np.quantile(e, 0.95)), "max": float(e.max()),
+                "mean": float(e.mean()), "surrogate_only_p95": float(np.quantile(e_pred, 0.95))}
+
+    res = {
+        "grid_points": n, "train_sims": cfg.n_train, "refined": int(len(idx)),
+        "refined_audit": int(is_aud.sum()), "check_points": int(len(chk)),
+        "check_points_refined": int(refined[chk].sum()),
+        "fc_mean_err": errs(STATS.index("fc_mean")),
+        "fc_sc_corr_err": errs(STATS.index("fc_sc_corr")),
+        "sync_index_err": errs(STATS.index("sync_index")),
+        "seconds": {"train_data": t_data, "train": tinfo["seconds"], "screen": t_screen,
+                    "refine": t_refine, "guided_total": t_guided,
+                    "plain": t_plain, "plain_is_extrapolated": not plain_full,
+                    "plain_sec_per_instance": sec_per_inst},
+        "time_ratio_guided_over_plain": t_guided / t_plain,
+        "train": {k: v for k, v in tinfo.items() if k != "history"},
+        "flags_nonfinite": int(((ftrain & 1) != 0).sum() + ((fref & 1) != 0).sum()),
+    }
+    res["passes_err_bound"] = res["fc_mean_err"]["p95"] < cfg.err_bound
+    return res, {"guided": guided, "pred": Yhat, "idx": idx, "check": chk, "plain": Yplain,
+                 "grid": G, "train_X": _points(train), "train_Y": Ytrain}

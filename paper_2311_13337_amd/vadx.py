@@ -31,7 +31,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_set_launch", "vadx_set_noise_keys", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
-           "vadx_mlp_predict")
+           "vadx_mlp_predict", "vadx_mlp_select")
 MLP_PARAMS = 17926
 
 
@@ -121,6 +121,8 @@ def lib():
             "vadx_mlp_grad": (st, [vp, vp, vp, C.c_int64, vp, P(C.c_float)]),
             "vadx_mlp_train": (st, [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, vp]),
             "vadx_mlp_predict": (st, [vp, vp, C.c_int64, vp, vp, vp, C.c_int32, C.c_int32]),
+            "vadx_mlp_select": (st, [vp, vp, C.c_int64, C.c_int64, C.c_float, C.c_uint32, vp, vp,
+                                     C.c_int64, P(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -419,3 +421,18 @@ class Mlp:
             C.c_void_p(J.data_ptr()) if J is not None else None,
             C.c_void_p(sc.data_ptr()) if sc is not None else None, o0, o1))
         return Y, J, sc
+
+    def select(self, score, k, audit_frac, seed, sel, is_audit=None):
+        """Indices (into the device int64 tensor sel) of the k largest scores
+        plus the audit sample; returns their count."""
+        torch = self.torch
+        assert score.is_cuda and score.dtype == torch.float32 and score.is_contiguous()
+        assert sel.is_cuda and sel.dtype == torch.int64
+        assert is_audit is None or (is_audit.dtype == torch.uint8 and is_audit.numel() >= sel.numel())
+        n_sel = C.c_int64()
+        self._check(lib().vadx_mlp_select(
+            self.h, C.c_void_p(score.data_ptr()), score.numel(), int(k), float(audit_frac),
+            int(seed) & 0xFFFFFFFF, C.c_void_p(sel.data_ptr()),
+            C.c_void_p(is_audit.data_ptr()) if is_audit is not None else None, sel.numel(),
+            C.byref(n_sel)))
+        return n_sel.value

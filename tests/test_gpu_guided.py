@@ -1,0 +1,105 @@
+"""Screening selection and the surrogate-guided sweep on the GPU.
+
+Selection is checked exactly against a host computation of its definition
+(top k by score with ties to the lower index, plus the audit rule evaluated
+with an independent Philox implementation). The guided sweep runs at a
+reduced size (12^4 grid, 1 s runs) where the plain sweep over the whole grid
+is cheap, so its error is measured at every grid point.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _philox_audit(seed, idx, frac):
+    """Independent host Philox4x32-10 (Salmon et al. 2011) of the audit draw:
+    key (seed, 0xA0D17), counter (i mod 2^32, i div 2^32, 0, 0), first word's
+    top 24 bits as a uniform in [0, 1)."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    c0 = (idx & 0xFFFFFFFF).astype(np.uint64)
+    c1 = (idx >> 32).astype(np.uint64)
+    c2 = np.zeros_like(c0)
+    c3 = np.zeros_like(c0)
+    k0, k1 = np.uint64(seed), np.uint64(0xA0D17)
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = c0 * np.uint64(M0)
+        p1 = c2 * np.uint64(M1)
+        n0 = (p1 >> np.uint64(32)) ^ c1 ^ k0
+        n2 = (p0 >> np.uint64(32)) ^ c3 ^ k1
+        c0, c1, c2, c3 = n0 & mask, p1 & mask, n2 & mask, p0 & mask
+        k0 = (k0 + np.uint64(W0)) & mask
+        k1 = (k1 + np.uint64(W1)) & mask
+    u = (c0 >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+    return u < np.float32(frac)
+
+
+def _expected(score, k, frac, seed):
+    n = score.size
+    order = np.lexsort((np.arange(n), -score.astype(np.float64)))   # score desc, index asc
+    top = np.zeros(n, bool)
+    top[order[:k]] = True
+    aud = ~top & _philox_audit(seed, np.arange(n, dtype=np.int64), frac) if frac > 0 else \
+        np.zeros(n, bool)
+    sel = np.nonzero(top | aud)[0]
+    return sel, aud[sel]
+
+
+@pytest.mark.parametrize("n,k,frac,ties", [(1, 1, 0.0, False), (1000, 50, 0.01, False),
+                                          (100003, 5000, 0.01, True), (70000, 0, 0.05, False),
+                                          (5000, 5000, 0.0, False), (4097, 3000, 1.0, True)])
+def test_select_matches_definition(n, k, frac, ties):
+    import torch
+
+    from paper_2311_13337_amd import inputs, vadx
+    rng = np.random.default_rng(n + k)
+    score = rng.gamma(2.0, 1.0, n).astype(np.float32)
+    if ties:
+        score = np.round(score * 4) / 4                       # many equal scores
+    net = vadx.Mlp(inputs.mlp_init_params(0), (0, 0, 0, 0), (1, 1, 1, 1))
+    d = torch.from_numpy(score).cuda()
+    cap = n + 16
+    sel = torch.empty(cap, dtype=torch.int64, device="cuda")
+    aud = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    m = net.select(d, k, frac, 7, sel, aud)
+    want, want_aud = _expected(score, k, frac, 7)
+    assert m == want.size
+    assert np.array_equal(sel[:m].cpu().numpy(), want)
+    assert np.array_equal(aud[:m].cpu().numpy().astype(bool), want_aud)
+    if m > 0:
+        with pytest.raises(vadx.VadxError):
+            net.select(d, k, frac, 7, sel[: m - 1], aud)
+
+
+def test_guided_sweep_small_grid():
+    """12^4 grid, 1 s runs: guided = 2048 training runs + 6% of the grid
+    simulated; the error against the plain sweep is measured at every point,
+    refined points reproduce their plain values exactly, and the guided error
+    is compared with what the same simulation budget gives without the
+    network (nearest simulated training point)."""
+    from paper_2311_13337_amd import guided, inputs
+    cfg = guided.GuidedConfig(grid_res=12, n_train=2048,
+                              run=inputs.RunConfig(n_steps=10000, transient_steps=2000),
+                              max_epochs=300, patience=40, chunk=8192)
+    res, data = guided.guided_sweep(cfg, plain_full=True)
+    print("[guided-small]", {k: v for k, v in res.items() if k != "train"}, flush=True)
+    g, p, idx = data["guided"], data["plain"], data["idx"]
+    assert np.array_equal(g[idx], p[idx])               # refined points are plain runs
+    assert res["refined"] < 0.08 * res["grid_points"]
+    # the network against no network at the same budget: predict each grid
+    # point by its nearest training point (normalised box distance)
+    lo = np.array([b[0] for b in guided.BOX], np.float32)
+    hi = np.array([b[1] for b in guided.BOX], np.float32)
+    G = (data["grid"] - lo) / (hi - lo)
+    Tn = (data["train_X"] - lo) / (hi - lo)
+    nn = np.empty(len(G), np.int64)
+    for c0 in range(0, len(G), 2048):
+        d2 = ((G[c0:c0 + 2048, None, :] - Tn[None, :, :]) ** 2).sum(-1)
+        nn[c0:c0 + 2048] = d2.argmin(1)
+    base = data["train_Y"][nn]
+    base[idx] = p[idx]
+    e_base = np.quantile(np.abs(base[:, 0] - p[:, 0]), 0.95)
+    print(f"[guided-small] fc_mean p95 error: guided {res['fc_mean_err']['p95']:.4f}, "
+          f"nearest-sample baseline {e_base:.4f}", flush=True)
+    assert res["fc_mean_err"]["p95"] < e_base
