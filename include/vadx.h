@@ -189,6 +189,14 @@ vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,
  * Results do not depend on the shape. */
 vadx_status vadx_set_launch(vadx_ctx *ctx, int32_t mode, int32_t wg_instances, int32_t item_steps);
 
+/* Graph replay: with on = 1, vadx_integrate records the whole run (flag
+ * clears, integration launches, FC) once into a HIP graph and replays it on
+ * later calls with the same plan and workspace; the first call after
+ * vadx_plan, a new workspace or vadx_set_graph re-records. Results are those
+ * of the eager launches. Runs with timing enabled stay eager. Waits for the
+ * context's stream. */
+vadx_status vadx_set_graph(vadx_ctx *ctx, int32_t on);
+
 /* Kernel timing: when enabled, HIP events on the context's stream bracket every
  * launch of the integration kernel; vadx_kernel_time reports their count and
  * summed duration (ms) since the last reset, and the duration of the FC

@@ -101,6 +101,7 @@ hipError_t launch_delays(int n_tables, const DelayTableDev *tables, const ConnDe
                          int32_t *packed, int max_nnz, hipStream_t s);
 // q == nullptr: one workgroup per group over [a.n_begin, a.n_end); otherwise the
 // persistent kernel with `grid` workgroups draining the queue.
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
                             const QueueArgs *q, int grid, hipStream_t s);
 int persistent_blocks_per_cu(int block, int block_threads);

@@ -324,6 +324,24 @@ __global__ __launch_bounds__(512) void integrate_persistent_kernel(IntegrateArgs
     }
 }
 
+// Clears n words (a kernel rather than a memset node, so a captured run
+// graph holds kernels only).
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
 __global__ void queue_reset_kernel(QueueArgs q)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

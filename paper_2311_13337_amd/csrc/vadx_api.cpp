@@ -100,6 +100,12 @@ struct vadx_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_int, ev_fc;
     // launch shape: 0 = persistent work queue (default), 1 = one workgroup per group
     int launch_mode = 0;
+    // graph replay of whole runs
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    void *g_ws = nullptr;
+    uint64_t g_epoch = 0, plan_epoch = 0;
     int wg_instances_override = 0;
     int item_steps = 1000;
     int cus = 0;
@@ -187,6 +193,8 @@ void vadx_destroy(vadx_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &e : c->ev_int) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto &e : c->ev_fc) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     c->rowptr.release(); c->colidx.release(); c->weight.release(); c->edge_len.release();
@@ -505,6 +513,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->plan_run = *r;
     c->planned = true;
+    ++c->plan_epoch;
     c->ran = false;
     *bytes = c->ws_bytes;
     return VADX_OK;
@@ -550,19 +559,14 @@ static vadx_status record(vadx_ctx *c, std::vector<std::pair<hipEvent_t, hipEven
     return VADX_OK;
 }
 
-vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_bytes)
+// Enqueues one whole run (flag clear, integration chunks, FC and statistics)
+// on `st`. With timing on, events bracket the launches (eager runs only).
+static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStream_t st,
+                               bool timed)
 {
-    if (!c) return VADX_E_ARG;
-    if (!run_ok(c, r)) return fail(c, VADX_E_ARG, "invalid run settings");
-    if (!c->planned || std::memcmp(&c->plan_run, r, sizeof(vadx_run)) != 0)
-        return fail(c, VADX_E_STATE, "run differs from the last vadx_plan (call vadx_plan first)");
-    if (!ws || ((uintptr_t)ws & 255u)) return fail(c, VADX_E_ARG, "workspace must be 256-byte aligned");
-    if (ws_bytes < c->ws_bytes)
-        return fail(c, VADX_E_OOM, "workspace of %zu bytes < planned %zu", ws_bytes, c->ws_bytes);
-    HIP_TRY(c, hipSetDevice(c->device));
     const int64_t ni = (int64_t)c->S.size();
     uint32_t *flags = (uint32_t *)((char *)ws + c->off_flags);
-    HIP_TRY(c, hipMemsetAsync(flags, 0, (size_t)ni * 4, c->stream));
+    HIP_TRY(c, launch_fill_u32(flags, ni, 0u, st));
     IntegrateArgs a{};
     a.M = make_kmodel(c->model, r->dt_ms);
     a.inst = c->d_inst.p;
@@ -602,23 +606,20 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
         const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads);
         if (per_cu <= 0) return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", c->wg_threads);
         grid = std::min(ng, per_cu * c->cus);
-        HIP_TRY(c, hipMemsetAsync(q.status, 0, 4, c->stream));
+        HIP_TRY(c, launch_fill_u32(q.status, 1, 0u, st));
     }
     for (int64_t n0 = 0; n0 < r->n_steps; n0 += chunk) {
         a.n_begin = n0;
         a.n_end = std::min<int64_t>(r->n_steps, n0 + chunk);
         hipEvent_t stop = nullptr;
-        if (c->timing) { vadx_status st = record(c, c->ev_int, &stop); if (st) return st; }
+        if (timed) { vadx_status e = record(c, c->ev_int, &stop); if (e) return e; }
         if (c->launch_mode == 0) {
             q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
-            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, &q, grid, c->stream));
+            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, &q, grid, st));
         } else {
-            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, nullptr, ng, c->stream));
+            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, nullptr, ng, st));
         }
-        if (c->timing) HIP_TRY(c, hipEventRecord(stop, c->stream));
-    }
-    if (r->n_steps == 0) {
-        // nothing integrated: state is the initial state, no samples
+        if (timed) HIP_TRY(c, hipEventRecord(stop, st));
     }
     FcArgs f{};
     f.inst = c->d_inst.p;
@@ -630,11 +631,65 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
     f.n_samples = c->n_samples;
     f.min_var = r->fc_min_std * r->fc_min_std;
     hipEvent_t stop = nullptr;
-    if (c->timing) { vadx_status st = record(c, c->ev_fc, &stop); if (st) return st; }
-    HIP_TRY(c, launch_fc_stats(f, ni, c->stream));
-    if (c->timing) HIP_TRY(c, hipEventRecord(stop, c->stream));
+    if (timed) { vadx_status e = record(c, c->ev_fc, &stop); if (e) return e; }
+    HIP_TRY(c, launch_fc_stats(f, ni, st));
+    if (timed) HIP_TRY(c, hipEventRecord(stop, st));
+    return VADX_OK;
+}
+
+static void drop_graph(vadx_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_ws = nullptr;
+}
+
+vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_bytes)
+{
+    if (!c) return VADX_E_ARG;
+    if (!run_ok(c, r)) return fail(c, VADX_E_ARG, "invalid run settings");
+    if (!c->planned || std::memcmp(&c->plan_run, r, sizeof(vadx_run)) != 0)
+        return fail(c, VADX_E_STATE, "run differs from the last vadx_plan (call vadx_plan first)");
+    if (!ws || ((uintptr_t)ws & 255u)) return fail(c, VADX_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < c->ws_bytes)
+        return fail(c, VADX_E_OOM, "workspace of %zu bytes < planned %zu", ws_bytes, c->ws_bytes);
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!c->use_graph || c->timing) {
+        vadx_status e = enqueue_run(c, r, ws, c->stream, c->timing);
+        if (e) return e;
+    } else {
+        if (!c->gexec || c->g_ws != ws || c->g_epoch != c->plan_epoch) {
+            drop_graph(c);
+            if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            vadx_status e = enqueue_run(c, r, ws, c->cap_stream, false);
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(c->cap_stream, &g);
+            if (e) { if (g) (void)hipGraphDestroy(g); return e; }
+            if (ce != hipSuccess) return fail(c, VADX_E_HIP, "graph capture: %s", hipGetErrorString(ce));
+            hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                c->gexec = nullptr;
+                return fail(c, VADX_E_HIP, "graph instantiate: %s", hipGetErrorString(ie));
+            }
+            c->g_ws = ws;
+            c->g_epoch = c->plan_epoch;
+        }
+        HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+    }
     c->ws = ws;
     c->ran = true;
+    return VADX_OK;
+}
+
+vadx_status vadx_set_graph(vadx_ctx *c, int32_t on)
+{
+    if (!c) return VADX_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->use_graph = on != 0;
     return VADX_OK;
 }
 

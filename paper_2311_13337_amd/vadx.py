@@ -28,7 +28,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
            "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
-           "vadx_set_launch", "vadx_set_noise_keys", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
+           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select")
@@ -95,6 +95,7 @@ def lib():
             "vadx_set_batch": (st, [vp, C.c_int64, vp, vp, vp, vp, vp]),
             "vadx_set_trace": (st, [vp, C.c_int64, vp]),
             "vadx_set_noise_keys": (st, [vp, C.c_int64, vp]),
+            "vadx_set_graph": (st, [vp, C.c_int32]),
             "vadx_plan": (st, [vp, P(vadx_run), P(C.c_size_t)]),
             "vadx_integrate": (st, [vp, P(vadx_run), vp, C.c_size_t]),
             "vadx_sync": (st, [vp]),
@@ -199,6 +200,9 @@ class Context:
         self._keep = (arrs, cp)
         self._check(lib().vadx_set_batch(self.h, arrs[0].shape[0], *[_ptr(x) for x in arrs],
                                          None if cp is None else _ptr(cp)))
+
+    def vadx_set_graph(self, on: bool):
+        self._check(lib().vadx_set_graph(self.h, 1 if on else 0))
 
     def vadx_set_noise_keys(self, keys):
         a = np.ascontiguousarray(keys, np.uint32)

@@ -280,6 +280,37 @@ def test_noise_keys_reproduce_sweep_members():
         sw.ctx.vadx_set_noise_keys([1, 2])
 
 
+def test_graph_replay_matches_eager():
+    """Whole runs recorded once into a HIP graph and replayed: every replay,
+    with other eager GPU work and synchronisations in between, gives the bits
+    of the eager run."""
+    import torch
+    conn = inputs.synthetic_connectome(68)
+    batch = inputs.grid_small()
+    cfg = inputs.RunConfig(n_steps=600, transient_steps=100, seed=5)
+    eager = run_gpu("literature-B", [conn], batch, cfg)
+    want = ([eager.ctx.vadx_read_state(i) for i in range(8)],
+            [eager.ctx.vadx_read_fc(i) for i in range(8)], eager.stats())
+    sw = vadx.Sweep(0, gpu_model("literature-B"))
+    sw.add_connectome(conn)
+    sw.set_batch(batch)
+    sw.plan(vadx.make_run(cfg))
+    sw.ctx.vadx_set_graph(True)
+    for rep in range(3):
+        sw.integrate()
+        sw.sync()
+        for i in range(8):
+            assert np.array_equal(sw.ctx.vadx_read_state(i), want[0][i]), (rep, i)
+            assert np.array_equal(sw.ctx.vadx_read_fc(i), want[1][i]), (rep, i)
+        assert np.array_equal(sw.stats(), want[2])
+        # eager work of the program between replays
+        x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+        assert float(x.sum()) > 0
+        eager.integrate()
+        eager.sync()
+        torch.cuda.synchronize()
+
+
 def test_degenerate_runs():
     conn = inputs.synthetic_connectome(68)
     batch = inputs.grid_small().subset([0])
