@@ -9,7 +9,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <utility>
 #include <vector>
@@ -107,6 +109,7 @@ struct vadx_ctx {
     void *g_ws = nullptr;
     uint64_t g_epoch = 0, plan_epoch = 0;
     int wg_instances_override = 0;
+    int wg_lanes = 512;                  // lane budget per workgroup (autotuned)
     int item_steps = 1000;
     int cus = 0;
 };
@@ -448,7 +451,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     for (int64_t s = 0; s < ni;) {
         const int32_t cid = c->conn_of[order[s]];
         const int n = c->conns[cid].n;
-        int per = std::max(1, 512 / n);
+        int per = std::max(1, c->wg_lanes / n);
         if (c->wg_instances_override > 0) per = std::min(per, c->wg_instances_override);
         int64_t e = s;
         while (e < ni && e - s < per && c->conn_of[order[e]] == cid) ++e;
@@ -837,3 +840,175 @@ vadx_status vadx_kernel_time(vadx_ctx *c, int64_t *n_int, double *ms_int, int64_
 }
 
 } // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+// Key of a batch for the tuning cache: device, block length and the mix of
+// region counts (instance counts rounded to powers of two).
+static std::string tune_key(vadx_ctx *c)
+{
+    hipDeviceProp_t prop{};
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
+    std::map<int, int64_t> cls;
+    for (int32_t ci : c->conn_of) cls[c->conns[ci].n] += 1;
+    std::ostringstream k;
+    for (char ch : dev)
+        if (ch != '"' && ch != '\\' && ch != ':') k << ch;
+    k << "|B" << c->block;
+    for (auto &e : cls) {
+        int64_t p2 = 1;
+        while (p2 < e.second) p2 <<= 1;
+        k << "|n" << e.first << "x" << p2;
+    }
+    return k.str();
+}
+
+static bool tune_lookup(const char *path, const std::string &key, int *lanes, int *items)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line, q = "\"" + key + "\"";
+    while (std::getline(f, line)) {
+        const size_t at = line.find(q);
+        if (at == std::string::npos) continue;
+        int l = 0, it = 0;
+        const size_t pl = line.find("\"lanes\":", at), pi = line.find("\"item_steps\":", at);
+        if (pl == std::string::npos || pi == std::string::npos) continue;
+        if (std::sscanf(line.c_str() + pl + 8, "%d", &l) == 1 &&
+            std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 && l >= 64 && l <= 512 && it > 0) {
+            *lanes = l;
+            *items = it;
+            return true;
+        }
+    }
+    return false;
+}
+
+static void tune_store(const char *path, const std::string &key, int lanes, int items, double ms)
+{
+    if (!path) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line, q = "\"" + key + "\"";
+        while (std::getline(f, line))
+            if (line.find("\"lanes\":") != std::string::npos && line.find(q) == std::string::npos) {
+                while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+                keep.push_back(line);
+            }
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"lanes\": %d, \"item_steps\": %d, \"trial_ms\": %.3f}",
+                  key.c_str(), lanes, items, ms);
+    keep.push_back(buf);
+    std::ofstream o(path, std::ios::trunc);
+    o << "{\n";
+    for (size_t i = 0; i < keep.size(); ++i) o << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+    o << "}\n";
+}
+
+extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_bytes,
+                                     const char *cache_path, int32_t trial_steps,
+                                     int32_t *lanes_out, int32_t *item_steps_out)
+{
+    if (!c || !r || !ws || ((uintptr_t)ws & 255u) || trial_steps < 0)
+        return fail(c, VADX_E_ARG, "bad autotune arguments");
+    if (c->S.empty()) return fail(c, VADX_E_STATE, "no batch set");
+    if (!run_ok(c, r)) return fail(c, VADX_E_ARG, "invalid run settings");
+    HIP_TRY(c, hipSetDevice(c->device));
+    // trial runs: the same model and steps, no samples, no traces
+    vadx_run t = *r;
+    t.n_steps = trial_steps > 0 ? trial_steps : 2000;
+    t.transient_steps = t.n_steps;
+    t.n_trace_steps = 0;
+    t.chunk_steps = 0;
+    size_t need = 0;
+    const int saved_mode = c->launch_mode, saved_override = c->wg_instances_override;
+    const bool saved_graph = c->use_graph, saved_timing = c->timing;
+    std::vector<int64_t> saved_traced = c->traced;
+    c->traced.clear();
+    c->launch_mode = 0;
+    c->wg_instances_override = 0;
+    c->use_graph = false;
+    c->timing = false;
+    int max_n = 1;
+    for (int32_t ci : c->conn_of) max_n = std::max(max_n, c->conns[ci].n);
+    vadx_status result = VADX_OK;
+    int best_l = 512, best_i = 1000;
+    double best_ms = -1.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto restore = [&]() {
+        c->launch_mode = saved_mode;
+        c->wg_instances_override = saved_override;
+        c->use_graph = saved_graph;
+        c->timing = saved_timing;
+        c->traced = saved_traced;
+        c->planned = false;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    auto trial = [&](int lanes, int items, double *ms) -> vadx_status {
+        c->wg_lanes = lanes;
+        c->item_steps = items;
+        c->planned = false;
+        vadx_status st = vadx_plan(c, &t, &need);
+        if (st) return st;
+        if (need > ws_bytes) return fail(c, VADX_E_OOM, "workspace too small for the trial runs");
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        st = enqueue_run(c, &t, ws, c->stream, false);
+        if (st) return st;
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        st = vadx_sync(c);
+        if (st) return st;
+        float f = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+        *ms = f;
+        return VADX_OK;
+    };
+    // the key needs the block length of this batch: plan once
+    c->wg_lanes = 512;
+    c->planned = false;
+    result = vadx_plan(c, &t, &need);
+    if (result) { restore(); return result; }
+    const std::string key = tune_key(c);
+    int cl = 0, ci = 0;
+    if (tune_lookup(cache_path, key, &cl, &ci)) {
+        best_l = cl;
+        best_i = ci;
+    } else {
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            restore();
+            return fail(c, VADX_E_HIP, "event creation failed");
+        }
+        double ms = 0.0;
+        result = trial(512, 1000, &ms);       // warm-up (code load, caches)
+        const int l_lo = std::max(64, (max_n + 63) / 64 * 64);
+        for (int l = l_lo; l <= 512 && result == VADX_OK; l += 64) {
+            // skip budgets that give the same instances per workgroup as a larger one
+            bool same = false;
+            if (l + 64 <= 512) {
+                same = true;
+                for (int32_t cj : c->conn_of) {
+                    const int n = c->conns[cj].n;
+                    if (std::max(1, l / n) != std::max(1, (l + 64) / n)) { same = false; break; }
+                }
+            }
+            if (same) continue;
+            result = trial(l, 1000, &ms);
+            if (result == VADX_OK && (best_ms < 0 || ms < best_ms)) { best_ms = ms; best_l = l; best_i = 1000; }
+        }
+        for (int it : {250, 4000}) {
+            if (result) break;
+            result = trial(best_l, it, &ms);
+            if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; }
+        }
+        if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_ms);
+    }
+    restore();
+    if (result) return result;
+    c->wg_lanes = best_l;
+    c->item_steps = best_i;
+    if (lanes_out) *lanes_out = best_l;
+    if (item_steps_out) *item_steps_out = best_i;
+    return VADX_OK;
+}

@@ -311,6 +311,32 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
 
 
+def test_autotuner_choice_cached_and_result_unchanged(tmp_path):
+    """The autotuner picks a lane budget and queue item length for a mixed
+    batch, stores it in the JSON cache, reads it back without trials, and the
+    tuned shape gives the same bits as the default one."""
+    import json
+    conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
+    b = inputs.grid_uneven(60, seed=11)
+    cfg = inputs.RunConfig(n_steps=400, transient_steps=100, seed=6)
+    ref = run_gpu("literature-B", conns, b, cfg)
+    sw = vadx.Sweep(0, gpu_model("literature-B"))
+    ids = [sw.add_connectome(c) for c in conns]
+    sw.set_batch(b, conn_ids=ids)
+    sw.plan(vadx.make_run(cfg))
+    cache = str(tmp_path / "tune.json")
+    lanes, items = sw.autotune(cache, trial_steps=200)
+    assert 200 <= lanes <= 512 and lanes % 64 == 0 and items in (250, 1000, 4000)
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and list(entries.values())[0]["lanes"] == lanes
+    assert sw.autotune(cache, trial_steps=200) == (lanes, items)
+    sw.integrate()
+    sw.sync()
+    for i in range(len(b)):
+        assert np.array_equal(sw.ctx.vadx_read_state(i), ref.ctx.vadx_read_state(i))
+        assert np.array_equal(sw.ctx.vadx_read_fc(i), ref.ctx.vadx_read_fc(i))
+
+
 def test_degenerate_runs():
     conn = inputs.synthetic_connectome(68)
     batch = inputs.grid_small().subset([0])
