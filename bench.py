@@ -16,6 +16,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +32,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", choices=["uniform", "small"], default="uniform")
+    p.add_argument("--workload", choices=["uniform", "uneven", "small"], default="uniform")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the default launch shape instead of tuning it first")
+    p.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "vadx_tune.json"))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-instances", type=int, default=64)
     p.add_argument("--cpu-sample-steps", type=int, default=10000)
@@ -48,32 +52,43 @@ def parse():
 def workload(name):
     from paper_2311_13337_amd import inputs
     conn = inputs.synthetic_connectome(68)
+    if name == "uneven":
+        conns = [conn, inputs.synthetic_connectome(84), inputs.synthetic_connectome(200)]
+        return conns, inputs.grid_uneven(8192, seed=3), inputs.RUN_UNEVEN, (
+            "uneven batch in one persistent launch: 8192 instances, a third each on 68-, 84- and "
+            "200-region synthetic connectomes, S, b_e, a_e uniform in the sweep box, v uniform in "
+            "1-10 m/s (ring depths 21-2001 steps); 50000 Heun steps of 0.1 ms (5 s), FC after a "
+            "1 s transient")
     if name == "uniform":
-        return conn, inputs.grid_uniform(64, 64), inputs.RUN_UNIFORM, (
+        return [conn], inputs.grid_uniform(64, 64), inputs.RUN_UNIFORM, (
             "uniform sweep: 64x64 grid of (S in [0,0.5], b_e in [0,120] pA), a_e=0, v=4 m/s; "
             "4096 instances x 68 regions (synthetic connectome, 20% density, log-normal weights, "
             "10-200 mm tracts); 100000 Heun steps of 0.1 ms (10 s); FC over 9000 1-ms samples "
             "after a 1 s transient")
-    return conn, inputs.grid_small(), inputs.RUN_SMALL, (
+    return [conn], inputs.grid_small(), inputs.RUN_SMALL, (
         "small grid: 8 combos (S in {0.1,0.3} x b_e in {0,60} x a_e in {0,4}), v=4 m/s, "
         "68 regions, 10000 steps (1 s)")
 
 
-def cpu_baseline(conn, batch, cfg, n_inst, n_steps):
+def cpu_baseline(conns, batch, cfg, n_inst, n_steps):
     """The FP64 oracle on a bounded sample of the same workload (host cores)."""
     import numpy as np
 
     import oracle
     from paper_2311_13337_amd import inputs
     idx = np.linspace(0, len(batch) - 1, n_inst).round().astype(int)
-    sub = batch.subset(idx)
     scfg = inputs.RunConfig(dt_ms=cfg.dt_ms, n_steps=n_steps, transient_steps=0,
                             tavg_steps=cfg.tavg_steps, seed=cfg.seed)
     threads = os.cpu_count() or 1
+    units = 0.0
     t0 = time.perf_counter()
-    oracle.run(oracle.model(), scfg, conn, sub, inst_ids=idx, n_threads=threads)
+    for ci, conn in enumerate(conns):
+        sel = idx[batch.conn[idx] == ci]
+        if sel.size == 0:
+            continue
+        oracle.run(oracle.model(), scfg, conn, batch.subset(sel), inst_ids=sel, n_threads=threads)
+        units += sel.size * conn.n * n_steps * cfg.dt_ms / 1000.0
     wall = time.perf_counter() - t0
-    units = n_inst * conn.n * n_steps * cfg.dt_ms / 1000.0
     return {"value": units / wall, "unit": "instance-region-sim-s/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_inst} instances evenly spaced over the sweep x {n_steps} steps "
@@ -93,7 +108,7 @@ def main():
 
     from paper_2311_13337_amd import vadx
 
-    conn, batch, cfg, desc = workload(args.workload)
+    conns, batch, cfg, desc = workload(args.workload)
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -107,10 +122,14 @@ def main():
                                   transient_steps=min(cfg.transient_steps, args.run_steps // 2))
         desc = f"[profiling run, {args.run_steps} steps] " + desc
     sw = vadx.Sweep(0)
-    sw.add_connectome(conn)
-    sw.set_batch(batch)
+    ids = [sw.add_connectome(c) for c in conns]
+    sw.set_batch(batch, conn_ids=ids)
     run = vadx.make_run(cfg)
     sw.plan(run)
+    shape = {"lanes_per_workgroup": 512, "item_steps": 1000, "autotuned": False}
+    if not args.no_autotune:
+        lanes, items = sw.autotune(args.tune_cache)
+        shape = {"lanes_per_workgroup": lanes, "item_steps": items, "autotuned": True}
     ctx = sw.ctx
     for _ in range(args.warmup):
         sw.integrate()
@@ -128,18 +147,21 @@ def main():
     st = sw.stats()
     assert np.isfinite(st["fc_mean"]).all(), "non-finite FC mean"
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    n_inst, n_reg = len(batch), conn.n
+    n_inst = len(batch)
+    regions = np.array([c.n for c in conns], np.float64)[batch.conn]
+    region_total = float(regions.sum())
     sim_s = cfg.n_steps * cfg.dt_ms / 1000.0
-    value = n_inst * n_reg * sim_s / (ms_per_step / 1000.0)
+    value = region_total * sim_s / (ms_per_step / 1000.0)
 
     # roofline of the integration kernel: the kernel's own arithmetic per
     # region-step (counted with an operation-counting scalar) plus 2 FLOPs per
     # delayed-coupling edge, times the region-steps of one launch
     f32, f64, trans = vadx.vadx_region_step_ops(vadx.VADX_HEUN)
-    nnz = int((conn.weights != 0).sum())
-    flop_rs = f32 + f64 + 2.0 * nnz / n_reg + 1.0
+    nnz = np.array([(c.weights != 0).sum() for c in conns], np.float64)
+    edges = float(nnz[batch.conn].sum())
+    flop_rs = f32 + f64 + 2.0 * edges / region_total + 1.0
     launches_per_step = n_int / args.steps
-    rs_per_launch = n_inst * n_reg * cfg.n_steps / launches_per_step
+    rs_per_launch = region_total * cfg.n_steps / launches_per_step
     launch_ms = ms_int / n_int
     achieved = flop_rs * rs_per_launch / (launch_ms / 1000.0) / 1e12
     traffic = None
@@ -160,12 +182,14 @@ def main():
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": desc, "instances": n_inst, "regions": n_reg,
+           "config": {"workload": desc, "instances": n_inst,
+                      "regions": sorted({c.n for c in conns}),
+                      "region_instances_total": int(region_total),
                       "steps_per_run": cfg.n_steps, "dt_ms": cfg.dt_ms,
-                      "parallelism": "single GPU"},
+                      "parallelism": "single GPU", "launch_shape": shape},
            "roofline": roof}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(conn, batch, cfg, args.cpu_sample_instances,
+        out["cpu_baseline"] = cpu_baseline(conns, batch, cfg, args.cpu_sample_instances,
                                            args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
 
