@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--workload", choices=["uniform", "uneven", "small"], default="uniform")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch shape instead of tuning it first")
+    p.add_argument("--waves-per-simd", type=int, default=2, choices=[2, 4],
+                   help="register budget of the integration kernel when not autotuning")
     p.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "vadx_tune.json"))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-instances", type=int, default=64)
@@ -126,10 +128,14 @@ def main():
     sw.set_batch(batch, conn_ids=ids)
     run = vadx.make_run(cfg)
     sw.plan(run)
-    shape = {"lanes_per_workgroup": 512, "item_steps": 1000, "autotuned": False}
+    sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
+    sw.plan(run)
+    shape = {"lanes_per_workgroup": 512, "item_steps": 1000, "waves_per_simd": args.waves_per_simd,
+             "autotuned": False}
     if not args.no_autotune:
-        lanes, items = sw.autotune(args.tune_cache)
-        shape = {"lanes_per_workgroup": lanes, "item_steps": items, "autotuned": True}
+        lanes, items, waves = sw.autotune(args.tune_cache)
+        shape = {"lanes_per_workgroup": lanes, "item_steps": items, "waves_per_simd": waves,
+                 "autotuned": True}
     ctx = sw.ctx
     for _ in range(args.warmup):
         sw.integrate()

@@ -29,23 +29,31 @@
 
 namespace vadx {
 
-// FP32 constants of the model, derived on the host from vadx_model.
+// FP32 constants of the model, derived on the host from vadx_model
+// (make_kmodel in kmodel.h).
 struct KModel {
     float aE, aI;               // Q_e tau_e K_e, Q_i tau_i K_i  (nS per kHz)
-    float gL, Cm, Ee, Ei, Qe, Qi, tau_e, tau_i;
-    float KeTe2, KiTi2;         // K_e tau_e^2, K_i tau_i^2
+    float gL, Cm, Ee, Ei, tau_e, tau_i;
+    float ce, ci;               // K_e tau_e^2 Q_e^2, K_i tau_i^2 Q_i^2
+    float aEE, aEI, aII;        // aE^2, aE aI, aI^2
+    float bE, bI;               // aI (E_e - E_i), aE (E_i - E_e)
+    float EegL, EigL;           // E_e g_L, E_i g_L
+    float ce2bE, ci2bI;         // 2 c_e bE, 2 c_i bI
+    float ce2bE2, ci2bI2;       // 2 c_e bE^2, 2 c_i bI^2
     float EL[2];                // E_L for pop 0 (exc), 1 (inh)
     float gLEL[2];              // g_L E_L
-    float P[2][10];             // threshold polynomial coefficients (Table 1 order)
-    float mu_s, mu_o;           // m = mu_V * mu_s + mu_o
-    float sg_s, sg_o;           // s = sigma_V * sg_s + sg_o
-    float tn_s, tn_o;           // t = tau_V * tn_s + tn_o
+    // threshold polynomial (Table 1) in offsets d = u - pc of the raw
+    // coordinates u = (mu_V, sqrt2 sigma_V, tau_V) from the centre of their
+    // normalisation: P0 + plin . d + d . Hraw d / 2
+    float P0[2];
+    float plin[2][3];
+    float Hraw[2][6];           // 00 01 02 11 12 22
+    float pc[3];
     float invT, invNe, invNi;
     float inv_tauw[2], b_i, a_i;
     float cF[2][2];             // cF[pop][0 = exc input, 1 = inh input]
-    float inv_tauOU, ou_gain;   // 1/tau_OU, sigma_OU / tau_OU
+    float inv_tauOU;
     float w_noise, rate_max, x_floor;
-    float E_init, I_init;
 };
 
 // A value with its gradient (a = d/dxe, b = d/dxi) and Hessian.
@@ -154,6 +162,21 @@ template <class T> VADX_HD Jet<T> jofG(T f0, T f1, T f2, T aE, T aI)
     return Jet<T>{f0, f1 * aE, f1 * aI, f2e * aE, f2e * aI, f2 * aI * aI};
 }
 
+// x * f(G) for f known through f, f', f'' in G (aEE = aE^2, aEI = aE aI, aII = aI^2)
+template <class T>
+VADX_HD Jet<T> jmulG(const Jet<T> &x, T f0, T f1, T f2, T aE, T aI, T aEE, T aEI, T aII)
+{
+    T fa = f1 * aE, fb = f1 * aI, v2 = x.v * f2;
+    Jet<T> r;
+    r.v = x.v * f0;
+    r.a = fmaf_(x.a, f0, x.v * fa);
+    r.b = fmaf_(x.b, f0, x.v * fb);
+    r.aa = fmaf_(x.aa, f0, fmaf_(T(2) * x.a, fa, v2 * aEE));
+    r.ab = fmaf_(x.ab, f0, fmaf_(x.a, fb, fmaf_(x.b, fa, v2 * aEI)));
+    r.bb = fmaf_(x.bb, f0, fmaf_(T(2) * x.b, fb, v2 * aII));
+    return r;
+}
+
 // erfc with a shared exp(-z^2): Numerical Recipes' Chebyshev fit
 // erfc(|z|) = t exp(-z^2 + p(t)), t = 1/(1 + |z|/2), fractional error < 1.2e-7
 // (Press et al., Numerical Recipes, section 6.2). Returns erfc(z) and
@@ -185,51 +208,66 @@ template <bool EQ, class T>
 VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
 {
     const T aE = T(M.aE), aI = T(M.aI);
-    T ge = aE * xe, gi = aI * xi;
-    T G = T(M.gL) + ge + gi;
+    T G = fmaf_(aE, xe, fmaf_(aI, xi, T(M.gL)));
     T r = rcp(G);
-    // 1/G as a jet: (1/G)' = -r^2, (1/G)'' = 2 r^3
-    T r2 = r * r;
-    Jet<T> R = jofG(r, -r2, T(2) * r2 * r, aE, aI);
-    // mu_V and its closed-form derivatives
-    T mu = fmaf_(ge, T(M.Ee), fmaf_(gi, T(M.Ei), T(M.gLEL[pop]) - W)) * r;
-    T dEe = T(M.Ee) - mu, dEi = T(M.Ei) - mu;
-    T mu_a = aE * dEe * r, mu_b = aI * dEi * r;
+    T r2 = r * r, r3 = r2 * r;
+    // mu_V through A = (E_e - mu_V) G = alpha_e + beta_e xi (linear in xi) and
+    // B = (E_i - mu_V) G = alpha_i + beta_i xe (linear in xe): mu_V = E_e - A/G
+    T c0 = T(M.gLEL[pop]) - W;
+    T A = fmaf_(T(M.bE), xi, T(M.EegL) - c0);
+    T B = fmaf_(T(M.bI), xe, T(M.EigL) - c0);
+    T Ar2 = A * r2, Ar3 = T(2) * A * r3, bEr2 = T(M.bE) * r2;
     Jet<T> MU;
-    MU.v = mu;
-    MU.a = mu_a;
-    MU.b = mu_b;
-    MU.aa = T(-2) * aE * r * mu_a;
-    MU.ab = -r * fmaf_(aE, mu_b, aI * mu_a);
-    MU.bb = T(-2) * aI * r * mu_b;
-    muV_out = mu;
-    // PSP amplitudes U_s = Q_s (E_s - mu_V) / G
-    Jet<T> dE{dEe, -MU.a, -MU.b, -MU.aa, -MU.ab, -MU.bb};
-    Jet<T> dI{dEi, -MU.a, -MU.b, -MU.aa, -MU.ab, -MU.bb};
-    Jet<T> Ue2 = jsq(jmul(dE, R));   // (U_e / Q_e)^2
-    Jet<T> Ui2 = jsq(jmul(dI, R));   // (U_i / Q_i)^2
-    // A_e = K_e tau_e^2 Q_e^2 xe (U_e/Q_e)^2: times a function linear in xe
-    const T ce = T(M.KeTe2) * T(M.Qe) * T(M.Qe), ci = T(M.KiTi2) * T(M.Qi) * T(M.Qi);
-    T lxe = ce * xe, lxi = ci * xi;
-    Jet<T> Ae{lxe * Ue2.v, fmaf_(ce, Ue2.v, lxe * Ue2.a), lxe * Ue2.b,
-              fmaf_(T(2) * ce, Ue2.a, lxe * Ue2.aa), fmaf_(ce, Ue2.b, lxe * Ue2.ab),
-              lxe * Ue2.bb};
-    Jet<T> Ai{lxi * Ui2.v, lxi * Ui2.a, fmaf_(ci, Ui2.v, lxi * Ui2.b), lxi * Ui2.aa,
-              fmaf_(ci, Ui2.a, lxi * Ui2.ab), fmaf_(T(2) * ci, Ui2.b, lxi * Ui2.bb)};
+    MU.v = fmaf_(-A, r, T(M.Ee));
+    MU.a = Ar2 * aE;
+    MU.b = fmaf_(Ar2, aI, -T(M.bE) * r);
+    MU.aa = -Ar3 * T(M.aEE);
+    MU.ab = fmaf_(bEr2, aE, -Ar3 * T(M.aEI));
+    MU.bb = fmaf_(T(2) * bEr2, aI, -Ar3 * T(M.aII));
+    muV_out = MU.v;
+    // shot-noise weights A_s = K_s x_s (tau_s U_s)^2 with U_e = Q_e A/G^2,
+    // U_i = Q_i B/G^2: A_e + A_i = Pi / G^4 with the cubic
+    // Pi = c_e xe A^2 + c_i xi B^2 (c_s = K_s tau_s^2 Q_s^2), whose derivatives
+    // are exact polynomials
+    const T ce = T(M.ce), ci = T(M.ci);
+    T cexe = ce * xe, cixi = ci * xi;
+    T A2 = A * A, B2 = B * B;
+    Jet<T> PI;
+    PI.v = fmaf_(cexe, A2, cixi * B2);
+    PI.a = fmaf_(ce, A2, T(M.ci2bI) * xi * B);
+    PI.b = fmaf_(T(M.ce2bE) * xe, A, ci * B2);
+    PI.aa = T(M.ci2bI2) * xi;
+    PI.ab = fmaf_(T(M.ce2bE), A, T(M.ci2bI) * B);
+    PI.bb = T(M.ce2bE2) * xe;
     // d_s = 1/(C_m/G + tau_s) = G/(C_m + tau_s G): h' = C_m (d r)^2, h'' = -2 tau_s C_m (d r)^3
     T de = rcp(fmaf_(T(M.Cm), r, T(M.tau_e)));
     T qe = de * r;
     T he1 = T(M.Cm) * qe * qe;
     const T he2 = T(-2) * T(M.tau_e) * he1 * qe;
-    Jet<T> De = jofG(de, he1, he2, aE, aI);
-    Jet<T> As = jadd(Ae, Ai);
     Jet<T> S2, ITV, TV;                              // 2 sigma_V^2, 1/tau_V, tau_V
     if constexpr (EQ) {
-        S2 = jmul(As, De);
-        ITV = De;
+        // S2 = Pi phi(G), phi = d_e / G^4: (ln phi)' = -(3 + tau d_e)/G,
+        // phi'' = phi (12 + 6 tau d_e + 2 (tau d_e)^2) / G^2
+        T td = T(M.tau_e) * de;
+        T phi = r2 * r2 * de;
+        T phi1 = -phi * r * (T(3) + td);
+        T phi2 = phi * r2 * fmaf_(td, fmaf_(T(2), td, T(6)), T(12));
+        S2 = jmulG(PI, phi, phi1, phi2, aE, aI, T(M.aEE), T(M.aEI), T(M.aII));
+        ITV = jofG(de, he1, he2, aE, aI);
         // tau_V = T_eff + tau_e = C_m/G + tau_e
-        TV = jofG(fmaf_(T(M.Cm), r, T(M.tau_e)), -T(M.Cm) * r2, T(2) * T(M.Cm) * r2 * r, aE, aI);
+        TV = jofG(fmaf_(T(M.Cm), r, T(M.tau_e)), -T(M.Cm) * r2, T(2) * T(M.Cm) * r3, aE, aI);
     } else {
+        // A_e = c_e xe A^2 / G^4 and A_i = c_i xi B^2 / G^4 weighted separately
+        Jet<T> Ae, Ai;
+        Ae.v = cexe * A2; Ae.a = ce * A2; Ae.b = T(M.ce2bE) * xe * A;
+        Ae.aa = T(0); Ae.ab = T(M.ce2bE) * A; Ae.bb = T(M.ce2bE2) * xe;
+        Ai.v = cixi * B2; Ai.a = T(M.ci2bI) * xi * B; Ai.b = ci * B2;
+        Ai.aa = T(M.ci2bI2) * xi; Ai.ab = T(M.ci2bI) * B; Ai.bb = T(0);
+        T r4 = r2 * r2;
+        Jet<T> R4 = jofG(r4, T(-4) * r4 * r, T(20) * r4 * r2, aE, aI);
+        Ae = jmul(Ae, R4);
+        Ai = jmul(Ai, R4);
+        Jet<T> De = jofG(de, he1, he2, aE, aI);
         T di = rcp(fmaf_(T(M.Cm), r, T(M.tau_i)));
         T qi = di * r;
         T hi1 = T(M.Cm) * qi * qi;
@@ -239,6 +277,7 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
         // 1/tau_V = (A_e d_e + A_i d_i)/(A_e + A_i) = d_e + w (d_i - d_e) with
         // w = A_i/(A_e + A_i): a weighted mean of d_e, d_i whose derivatives do
         // not cancel when one source dominates (the ratio form loses them in FP32).
+        Jet<T> As = jadd(Ae, Ai);
         T ra = rcp(As.v);
         T ra2 = ra * ra;
         Jet<T> RA = jchain(As, ra, -ra2, T(2) * ra2 * ra);
@@ -253,31 +292,44 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
     T q = rsq(S2.v);
     T q2 = q * q, q3 = q2 * q;
     Jet<T> Q = jchain(S2, q, T(-0.5f) * q3, T(0.75f) * q3 * q2);
-    // sigma_V = S2 q / sqrt2
-    Jet<T> SQ = jmul(S2, Q);
-    // normalised polynomial coordinates
-    Jet<T> mm = jaffine(MU, T(M.mu_s), T(M.mu_o));
-    Jet<T> ss = jaffine(SQ, T(M.sg_s), T(M.sg_o));   // sg_s includes 1/sqrt2
-    Jet<T> tt = jaffine(TV, T(M.tn_s), T(M.tn_o));
-    const float *P = M.P[pop];
-    // V_thre - mu_V = P0 + m (P1 + P4 m + P7 s + P8 t) + s (P2 + P5 s + P9 t)
-    //                 + t (P3 + P6 t) - mu_V
-    Jet<T> c1 = jaffine(mm, T(P[4]), T(P[1]));
-    c1 = jadd(c1, jaffine(ss, T(P[7]), T(0)));
-    c1 = jadd(c1, jaffine(tt, T(P[8]), T(0)));
-    Jet<T> c2 = jaffine(ss, T(P[5]), T(P[2]));
-    c2 = jadd(c2, jaffine(tt, T(P[9]), T(0)));
-    Jet<T> c3 = jaffine(tt, T(P[6]), T(P[3]));
-    Jet<T> V = jadd(jadd(jmul(mm, c1), jmul(ss, c2)), jmul(tt, c3));
-    V = jadd(V, jaffine(MU, T(-1), T(P[0])));
+    // SQ = sqrt(S2) = sqrt2 sigma_V;  (x^1/2)' = q/2, '' = -q^3/4
+    Jet<T> SQ = jchain(S2, S2.v * q, T(0.5f) * q, T(-0.25f) * q3);
+    // V = V_thre - mu_V with the threshold polynomial p of Table 1 written in
+    // the offsets d = u - c of u = (mu_V, SQ, tau_V) from the centre c of its
+    // normalisation: p = P0 + L.d + d.H d / 2 with L_k = P_k s_k and the constant
+    // Hessian H_kl = s_k s_l d2p/dn_k dn_l, so grad p = L + H d and the jet of
+    // V follows from the jets of u by the chain rule.
+    const float *L = M.plin[pop], *Hr = M.Hraw[pop];
+    T d0 = MU.v - T(M.pc[0]), d1 = SQ.v - T(M.pc[1]), d2 = TV.v - T(M.pc[2]);
+    T k0 = fmaf_(T(Hr[0]), d0, fmaf_(T(Hr[1]), d1, fmaf_(T(Hr[2]), d2, T(L[0]))));
+    T k1 = fmaf_(T(Hr[1]), d0, fmaf_(T(Hr[3]), d1, fmaf_(T(Hr[4]), d2, T(L[1]))));
+    T k2 = fmaf_(T(Hr[2]), d0, fmaf_(T(Hr[4]), d1, fmaf_(T(Hr[5]), d2, T(L[2]))));
+    Jet<T> V;
+    V.v = fmaf_(T(0.5f), fmaf_(d0, T(L[0]) + k0, fmaf_(d1, T(L[1]) + k1, d2 * (T(L[2]) + k2))),
+                T(M.P0[pop]) - MU.v);
+    const T u0 = k0 - T(1);
+    V.a = fmaf_(u0, MU.a, fmaf_(k1, SQ.a, k2 * TV.a));
+    V.b = fmaf_(u0, MU.b, fmaf_(k1, SQ.b, k2 * TV.b));
+    // H u_a and H u_b
+    T wa0 = fmaf_(T(Hr[0]), MU.a, fmaf_(T(Hr[1]), SQ.a, T(Hr[2]) * TV.a));
+    T wa1 = fmaf_(T(Hr[1]), MU.a, fmaf_(T(Hr[3]), SQ.a, T(Hr[4]) * TV.a));
+    T wa2 = fmaf_(T(Hr[2]), MU.a, fmaf_(T(Hr[4]), SQ.a, T(Hr[5]) * TV.a));
+    T wb0 = fmaf_(T(Hr[0]), MU.b, fmaf_(T(Hr[1]), SQ.b, T(Hr[2]) * TV.b));
+    T wb1 = fmaf_(T(Hr[1]), MU.b, fmaf_(T(Hr[3]), SQ.b, T(Hr[4]) * TV.b));
+    T wb2 = fmaf_(T(Hr[2]), MU.b, fmaf_(T(Hr[4]), SQ.b, T(Hr[5]) * TV.b));
+    V.aa = fmaf_(u0, MU.aa, fmaf_(k1, SQ.aa, fmaf_(k2, TV.aa,
+           fmaf_(wa0, MU.a, fmaf_(wa1, SQ.a, wa2 * TV.a)))));
+    V.ab = fmaf_(u0, MU.ab, fmaf_(k1, SQ.ab, fmaf_(k2, TV.ab,
+           fmaf_(wa0, MU.b, fmaf_(wa1, SQ.b, wa2 * TV.b)))));
+    V.bb = fmaf_(u0, MU.bb, fmaf_(k1, SQ.bb, fmaf_(k2, TV.bb,
+           fmaf_(wb0, MU.b, fmaf_(wb1, SQ.b, wb2 * TV.b)))));
     Jet<T> Z = jmul(V, Q);                            // (V_thre - mu_V)/(sqrt2 sigma_V)
     T g, e;
     erfc_and_gauss(Z.v, g, e);
-    const T TWO_OVER_SQRTPI = T(1.1283791670955126f);
-    T g1 = -TWO_OVER_SQRTPI * e;
-    Jet<T> GZ = jchain(Z, g, g1, T(-2) * Z.v * g1);
-    Jet<T> F = jmul(GZ, ITV);
-    return jaffine(F, T(0.5f), T(0));
+    // F = erfc(Z) / (2 tau_V): the factor 1/2 rides on erfc's chain coefficients
+    T g1 = T(-0.5f * 1.1283791670955126f) * e;
+    Jet<T> GZ = jchain(Z, T(0.5f) * g, g1, T(-2) * Z.v * g1);
+    return jmul(GZ, ITV);
 }
 
 // Per-instance parameters.

@@ -276,8 +276,10 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 // memory), so the groups advance in step while every workgroup stays busy
 // until the queue is empty. The wait is bounded: on timeout the kernel
 // records an error and the workgroup stops.
-template <int B, bool EQ>
-__global__ __launch_bounds__(512) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
+// OCC: waves per SIMD the register allocation must allow (2: one 512-lane
+// workgroup per CU; 4: two, at the price of a few register spills per step).
+template <int B, bool EQ, int OCC>
+__global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
 {
     extern __shared__ float cbuf[];
     __shared__ int s_item;
@@ -349,7 +351,7 @@ __global__ void queue_reset_kernel(QueueArgs q)
     if (i < q.n_groups) q.done[i] = 0;
 }
 
-template <int B, bool EQ>
+template <int B, bool EQ, int OCC>
 static hipError_t launch_integrate_b(const IntegrateArgs &a, int n_groups, int block_threads,
                                      const QueueArgs *q, int grid, hipStream_t s)
 {
@@ -360,58 +362,67 @@ static hipError_t launch_integrate_b(const IntegrateArgs &a, int n_groups, int b
         hipLaunchKernelGGL(queue_reset_kernel, dim3((q->n_groups + 255) / 256), dim3(256), 0, s, *q);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((integrate_persistent_kernel<B, EQ>), dim3(grid), dim3(block_threads),
+        hipLaunchKernelGGL((integrate_persistent_kernel<B, EQ, OCC>), dim3(grid), dim3(block_threads),
                            lds, s, a, *q);
     }
     return hipGetLastError();
 }
 
-template <bool EQ>
+template <bool EQ, int OCC>
 static hipError_t launch_integrate_eq(const IntegrateArgs &a, int n_groups, int block_threads,
                                       const QueueArgs *q, int grid, hipStream_t s)
 {
     switch (a.block) {
-    case 1: return launch_integrate_b<1, EQ>(a, n_groups, block_threads, q, grid, s);
-    case 2: return launch_integrate_b<2, EQ>(a, n_groups, block_threads, q, grid, s);
-    case 4: return launch_integrate_b<4, EQ>(a, n_groups, block_threads, q, grid, s);
-    case 8: return launch_integrate_b<8, EQ>(a, n_groups, block_threads, q, grid, s);
-    case 16: return launch_integrate_b<16, EQ>(a, n_groups, block_threads, q, grid, s);
+    case 1: return launch_integrate_b<1, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 2: return launch_integrate_b<2, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 4: return launch_integrate_b<4, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 8: return launch_integrate_b<8, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 16: return launch_integrate_b<16, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
-                            const QueueArgs *q, int grid, hipStream_t s)
+                            const QueueArgs *q, int grid, int occ, hipStream_t s)
 {
-    if (a.M.tau_e == a.M.tau_i) return launch_integrate_eq<true>(a, n_groups, block_threads, q, grid, s);
-    return launch_integrate_eq<false>(a, n_groups, block_threads, q, grid, s);
+    const bool eq = a.M.tau_e == a.M.tau_i;
+    if (occ == 4)
+        return eq ? launch_integrate_eq<true, 4>(a, n_groups, block_threads, q, grid, s)
+                  : launch_integrate_eq<false, 4>(a, n_groups, block_threads, q, grid, s);
+    return eq ? launch_integrate_eq<true, 2>(a, n_groups, block_threads, q, grid, s)
+              : launch_integrate_eq<false, 2>(a, n_groups, block_threads, q, grid, s);
 }
 
-template <int B> static int resident_b(int block_threads)
+template <int B, int OCC> static int resident_b(int block_threads)
 {
     // both model variants have the same launch bounds and LDS use
     int per_cu = 0;
     size_t lds = (size_t)B * block_threads * sizeof(float);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_persistent_kernel<B, true>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_persistent_kernel<B, true, OCC>,
                                                      block_threads, lds) != hipSuccess)
         return 0;
     int per_cu2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, integrate_persistent_kernel<B, false>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, integrate_persistent_kernel<B, false, OCC>,
                                                      block_threads, lds) != hipSuccess)
         return 0;
     return per_cu < per_cu2 ? per_cu : per_cu2;
 }
 
-int persistent_blocks_per_cu(int block, int block_threads)
+template <int OCC> static int resident(int block, int block_threads)
 {
     switch (block) {
-    case 1: return resident_b<1>(block_threads);
-    case 2: return resident_b<2>(block_threads);
-    case 4: return resident_b<4>(block_threads);
-    case 8: return resident_b<8>(block_threads);
-    case 16: return resident_b<16>(block_threads);
+    case 1: return resident_b<1, OCC>(block_threads);
+    case 2: return resident_b<2, OCC>(block_threads);
+    case 4: return resident_b<4, OCC>(block_threads);
+    case 8: return resident_b<8, OCC>(block_threads);
+    case 16: return resident_b<16, OCC>(block_threads);
     default: return 0;
     }
+}
+
+int persistent_blocks_per_cu(int block, int block_threads, int occ)
+{
+    return occ == 4 ? resident<4>(block, block_threads) : resident<2>(block, block_threads);
 }
 
 // ------------------------------------------------------------------ FC and statistics
@@ -585,5 +596,6 @@ hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s)
     hipLaunchKernelGGL(fc_stats_kernel, dim3((unsigned)n_inst), dim3(kFcThreads), 0, s, a);
     return hipGetLastError();
 }
+
 
 } // namespace vadx

@@ -48,24 +48,7 @@ inline CF maxf_(CF a, CF b) { CF::flop(1); return mk<float>(std::fmax(a.v, b.v))
 
 #include "adex_model.h"
 
-namespace vadx {
-static KModel count_model()
-{
-    vadx_model m;
-    vadx_model_defaults(VADX_PRESET_LITERATURE_B, &m);
-    KModel k{};
-    k.aE = 3000.f; k.aI = 2500.f; k.gL = 10.f; k.Cm = 200.f; k.Ee = 0.f; k.Ei = -80.f;
-    k.Qe = 1.5f; k.Qi = 5.f; k.tau_e = 5.f; k.tau_i = 5.f; k.KeTe2 = 1e4f; k.KiTi2 = 2500.f;
-    k.EL[0] = -64.f; k.EL[1] = -65.f; k.gLEL[0] = -640.f; k.gLEL[1] = -650.f;
-    for (int i = 0; i < 10; ++i) { k.P[0][i] = (float)m.P_e[i]; k.P[1][i] = (float)m.P_i[i]; }
-    k.mu_s = 0.1f; k.mu_o = 6.f; k.sg_s = 0.11785f; k.sg_o = -0.6667f; k.tn_s = 0.05f;
-    k.tn_o = -0.5f; k.invT = 0.05f; k.invNe = 1.25e-4f; k.invNi = 5e-4f;
-    k.inv_tauw[0] = 0.002f; k.inv_tauw[1] = 1.f; k.cF[0][0] = k.cF[1][0] = 3e-4f;
-    k.inv_tauOU = 0.2f; k.ou_gain = 2e-4f; k.w_noise = 1e-3f; k.rate_max = 1.f;
-    k.x_floor = 1e-6f; k.E_init = 0.004f; k.I_init = 0.01f;
-    return k;
-}
-} // namespace vadx
+#include "kmodel.h"
 
 extern "C" vadx_status vadx_region_step_ops(int32_t integrator, double *flop32, double *flop64,
                                             double *transcendental)
@@ -74,10 +57,10 @@ extern "C" vadx_status vadx_region_step_ops(int32_t integrator, double *flop32, 
     if (!flop32 || !flop64 || !transcendental || (integrator != 0 && integrator != 1))
         return VADX_E_ARG;
     g_tally = OpTally{};
-    KModel M = count_model();
-    CD X[8] = {CD(0.004), CD(0.01), CD(2e-6), CD(4e-6), CD(1e-5), CD(20.0), CD(0.0), CD(1e-4)};
     vadx_model mm;
     vadx_model_defaults(VADX_PRESET_LITERATURE_B, &mm);
+    KModel M = make_kmodel(mm);
+    CD X[8] = {CD(0.004), CD(0.01), CD(2e-6), CD(4e-6), CD(1e-5), CD(20.0), CD(0.0), CD(1e-4)};
     if (mm.tau_e == mm.tau_i)
         step_region<true, CF, CD>(M, integrator, CD(0.1), X, CF(1e-3f), CF(30.f), CF(2.f), CD(1e-5));
     else

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "kmodel.h"
 #include "vadx.h"
 
 using namespace vadx;
@@ -110,6 +111,7 @@ struct vadx_ctx {
     uint64_t g_epoch = 0, plan_epoch = 0;
     int wg_instances_override = 0;
     int wg_lanes = 512;                  // lane budget per workgroup (autotuned)
+    int occ = 2;                         // waves per SIMD of the persistent kernel (autotuned)
     int item_steps = 1000;
     int cus = 0;
 };
@@ -522,34 +524,6 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     return VADX_OK;
 }
 
-static KModel make_kmodel(const vadx_model &m, double dt)
-{
-    (void)dt;
-    KModel k{};
-    k.aE = (float)(m.Q_e * m.tau_e * m.K_e);
-    k.aI = (float)(m.Q_i * m.tau_i * m.K_i);
-    k.gL = (float)m.g_L; k.Cm = (float)m.C_m; k.Ee = (float)m.E_e; k.Ei = (float)m.E_i;
-    k.Qe = (float)m.Q_e; k.Qi = (float)m.Q_i; k.tau_e = (float)m.tau_e; k.tau_i = (float)m.tau_i;
-    k.KeTe2 = (float)(m.K_e * m.tau_e * m.tau_e);
-    k.KiTi2 = (float)(m.K_i * m.tau_i * m.tau_i);
-    k.EL[0] = (float)m.E_L_e; k.EL[1] = (float)m.E_L_i;
-    k.gLEL[0] = (float)(m.g_L * m.E_L_e); k.gLEL[1] = (float)(m.g_L * m.E_L_i);
-    for (int i = 0; i < 10; ++i) { k.P[0][i] = (float)m.P_e[i]; k.P[1][i] = (float)m.P_i[i]; }
-    k.mu_s = (float)(1.0 / m.dmuV0); k.mu_o = (float)(-m.muV0 / m.dmuV0);
-    k.sg_s = (float)(1.0 / (std::sqrt(2.0) * m.dsV0)); k.sg_o = (float)(-m.sV0 / m.dsV0);
-    k.tn_s = (float)(m.g_L / (m.C_m * m.dtN0)); k.tn_o = (float)(-m.tN0 / m.dtN0);
-    k.invT = (float)(1.0 / m.T); k.invNe = (float)(1.0 / m.N_e); k.invNi = (float)(1.0 / m.N_i);
-    k.inv_tauw[0] = (float)(1.0 / m.tau_w_e); k.inv_tauw[1] = (float)(1.0 / m.tau_w_i);
-    k.b_i = (float)m.b_i; k.a_i = (float)m.a_i;
-    k.cF[0][0] = (float)m.cF_ee; k.cF[0][1] = (float)m.cF_ei;
-    k.cF[1][0] = (float)m.cF_ie; k.cF[1][1] = (float)m.cF_ii;
-    k.inv_tauOU = (float)(1.0 / m.tau_OU);
-    k.ou_gain = (float)(m.sigma_OU / m.tau_OU);
-    k.w_noise = (float)m.w_noise; k.rate_max = (float)m.rate_max; k.x_floor = (float)m.x_floor;
-    k.E_init = (float)m.E_init; k.I_init = (float)m.I_init;
-    return k;
-}
-
 static vadx_status record(vadx_ctx *c, std::vector<std::pair<hipEvent_t, hipEvent_t>> &evs,
                           hipEvent_t *start)
 {
@@ -571,7 +545,7 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     uint32_t *flags = (uint32_t *)((char *)ws + c->off_flags);
     HIP_TRY(c, launch_fill_u32(flags, ni, 0u, st));
     IntegrateArgs a{};
-    a.M = make_kmodel(c->model, r->dt_ms);
+    a.M = make_kmodel(c->model);
     a.inst = c->d_inst.p;
     a.perm = c->d_perm.p;
     a.groups = c->d_groups.p;
@@ -606,7 +580,7 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
         q.n_groups = ng;
         q.item_steps = std::max<int64_t>(c->item_steps / c->block, 1) * c->block;
         q.max_spins = 1u << 26;
-        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads);
+        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads, c->occ);
         if (per_cu <= 0) return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", c->wg_threads);
         grid = std::min(ng, per_cu * c->cus);
         HIP_TRY(c, launch_fill_u32(q.status, 1, 0u, st));
@@ -618,9 +592,9 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
         if (timed) { vadx_status e = record(c, c->ev_int, &stop); if (e) return e; }
         if (c->launch_mode == 0) {
             q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
-            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, &q, grid, st));
+            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, &q, grid, c->occ, st));
         } else {
-            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, nullptr, ng, st));
+            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, nullptr, ng, 2, st));
         }
         if (timed) HIP_TRY(c, hipEventRecord(stop, st));
     }
@@ -683,6 +657,15 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
     }
     c->ws = ws;
     c->ran = true;
+    return VADX_OK;
+}
+
+vadx_status vadx_set_waves_per_simd(vadx_ctx *c, int32_t waves)
+{
+    if (!c) return VADX_E_ARG;
+    if (waves != 0 && waves != 2 && waves != 4) return fail(c, VADX_E_ARG, "waves per SIMD must be 2 or 4");
+    c->occ = waves == 0 ? 2 : waves;
+    c->planned = false;
     return VADX_OK;
 }
 
@@ -863,7 +846,7 @@ static std::string tune_key(vadx_ctx *c)
     return k.str();
 }
 
-static bool tune_lookup(const char *path, const std::string &key, int *lanes, int *items)
+static bool tune_lookup(const char *path, const std::string &key, int *lanes, int *items, int *occ)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -871,20 +854,25 @@ static bool tune_lookup(const char *path, const std::string &key, int *lanes, in
     while (std::getline(f, line)) {
         const size_t at = line.find(q);
         if (at == std::string::npos) continue;
-        int l = 0, it = 0;
+        int l = 0, it = 0, w = 0;
         const size_t pl = line.find("\"lanes\":", at), pi = line.find("\"item_steps\":", at);
-        if (pl == std::string::npos || pi == std::string::npos) continue;
+        const size_t pw = line.find("\"waves_per_simd\":", at);
+        if (pl == std::string::npos || pi == std::string::npos || pw == std::string::npos) continue;
         if (std::sscanf(line.c_str() + pl + 8, "%d", &l) == 1 &&
-            std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 && l >= 64 && l <= 512 && it > 0) {
+            std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 &&
+            std::sscanf(line.c_str() + pw + 17, "%d", &w) == 1 && l >= 64 && l <= 512 && it > 0 &&
+            (w == 2 || w == 4)) {
             *lanes = l;
             *items = it;
+            *occ = w;
             return true;
         }
     }
     return false;
 }
 
-static void tune_store(const char *path, const std::string &key, int lanes, int items, double ms)
+static void tune_store(const char *path, const std::string &key, int lanes, int items, int occ,
+                       double ms)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -898,8 +886,9 @@ static void tune_store(const char *path, const std::string &key, int lanes, int 
             }
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"lanes\": %d, \"item_steps\": %d, \"trial_ms\": %.3f}",
-                  key.c_str(), lanes, items, ms);
+    std::snprintf(buf, sizeof(buf),
+                  "  \"%s\": {\"lanes\": %d, \"item_steps\": %d, \"waves_per_simd\": %d, \"trial_ms\": %.3f}",
+                  key.c_str(), lanes, items, occ, ms);
     keep.push_back(buf);
     std::ofstream o(path, std::ios::trunc);
     o << "{\n";
@@ -909,7 +898,8 @@ static void tune_store(const char *path, const std::string &key, int lanes, int 
 
 extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_bytes,
                                      const char *cache_path, int32_t trial_steps,
-                                     int32_t *lanes_out, int32_t *item_steps_out)
+                                     int32_t *lanes_out, int32_t *item_steps_out,
+                                     int32_t *waves_out)
 {
     if (!c || !r || !ws || ((uintptr_t)ws & 255u) || trial_steps < 0)
         return fail(c, VADX_E_ARG, "bad autotune arguments");
@@ -924,6 +914,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     t.chunk_steps = 0;
     size_t need = 0;
     const int saved_mode = c->launch_mode, saved_override = c->wg_instances_override;
+    const int saved_occ = c->occ;
     const bool saved_graph = c->use_graph, saved_timing = c->timing;
     std::vector<int64_t> saved_traced = c->traced;
     c->traced.clear();
@@ -934,10 +925,11 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     int max_n = 1;
     for (int32_t ci : c->conn_of) max_n = std::max(max_n, c->conns[ci].n);
     vadx_status result = VADX_OK;
-    int best_l = 512, best_i = 1000;
+    int best_l = 512, best_i = 1000, best_w = 2;
     double best_ms = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto restore = [&]() {
+        c->occ = saved_occ;
         c->launch_mode = saved_mode;
         c->wg_instances_override = saved_override;
         c->use_graph = saved_graph;
@@ -947,9 +939,10 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    auto trial = [&](int lanes, int items, double *ms) -> vadx_status {
+    auto trial = [&](int lanes, int items, int occ, double *ms) -> vadx_status {
         c->wg_lanes = lanes;
         c->item_steps = items;
+        c->occ = occ;
         c->planned = false;
         vadx_status st = vadx_plan(c, &t, &need);
         if (st) return st;
@@ -971,17 +964,18 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     result = vadx_plan(c, &t, &need);
     if (result) { restore(); return result; }
     const std::string key = tune_key(c);
-    int cl = 0, ci = 0;
-    if (tune_lookup(cache_path, key, &cl, &ci)) {
+    int cl = 0, ci = 0, cw = 0;
+    if (tune_lookup(cache_path, key, &cl, &ci, &cw)) {
         best_l = cl;
         best_i = ci;
+        best_w = cw;
     } else {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             restore();
             return fail(c, VADX_E_HIP, "event creation failed");
         }
         double ms = 0.0;
-        result = trial(512, 1000, &ms);       // warm-up (code load, caches)
+        result = trial(512, 1000, 2, &ms);    // warm-up (code load, caches)
         const int l_lo = std::max(64, (max_n + 63) / 64 * 64);
         for (int l = l_lo; l <= 512 && result == VADX_OK; l += 64) {
             // skip budgets that give the same instances per workgroup as a larger one
@@ -994,20 +988,27 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
                 }
             }
             if (same) continue;
-            result = trial(l, 1000, &ms);
-            if (result == VADX_OK && (best_ms < 0 || ms < best_ms)) { best_ms = ms; best_l = l; best_i = 1000; }
+            for (int w : {2, 4}) {
+                if (result) break;
+                result = trial(l, 1000, w, &ms);
+                if (result == VADX_OK && (best_ms < 0 || ms < best_ms)) {
+                    best_ms = ms; best_l = l; best_i = 1000; best_w = w;
+                }
+            }
         }
         for (int it : {250, 4000}) {
             if (result) break;
-            result = trial(best_l, it, &ms);
+            result = trial(best_l, it, best_w, &ms);
             if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; }
         }
-        if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_ms);
+        if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_w, best_ms);
     }
     restore();
     if (result) return result;
     c->wg_lanes = best_l;
     c->item_steps = best_i;
+    c->occ = best_w;
+    if (waves_out) *waves_out = best_w;
     if (lanes_out) *lanes_out = best_l;
     if (item_steps_out) *item_steps_out = best_i;
     return VADX_OK;

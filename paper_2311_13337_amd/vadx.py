@@ -28,7 +28,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
            "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
-           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
+           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_set_waves_per_simd", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select")
@@ -97,7 +97,8 @@ def lib():
             "vadx_set_noise_keys": (st, [vp, C.c_int64, vp]),
             "vadx_set_graph": (st, [vp, C.c_int32]),
             "vadx_autotune": (st, [vp, P(vadx_run), vp, C.c_size_t, C.c_char_p, C.c_int32,
-                                   P(C.c_int32), P(C.c_int32)]),
+                                   P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
+            "vadx_set_waves_per_simd": (st, [vp, C.c_int32]),
             "vadx_plan": (st, [vp, P(vadx_run), P(C.c_size_t)]),
             "vadx_integrate": (st, [vp, P(vadx_run), vp, C.c_size_t]),
             "vadx_sync": (st, [vp]),
@@ -204,11 +205,14 @@ class Context:
                                          None if cp is None else _ptr(cp)))
 
     def vadx_autotune(self, run, ws_ptr, ws_bytes, cache_path=None, trial_steps=0):
-        lanes, items = C.c_int32(), C.c_int32()
+        lanes, items, waves = C.c_int32(), C.c_int32(), C.c_int32()
         self._check(lib().vadx_autotune(self.h, C.byref(run), C.c_void_p(ws_ptr), ws_bytes,
                                         cache_path.encode() if cache_path else None, trial_steps,
-                                        C.byref(lanes), C.byref(items)))
-        return lanes.value, items.value
+                                        C.byref(lanes), C.byref(items), C.byref(waves)))
+        return lanes.value, items.value, waves.value
+
+    def vadx_set_waves_per_simd(self, waves: int):
+        self._check(lib().vadx_set_waves_per_simd(self.h, waves))
 
     def vadx_set_graph(self, on: bool):
         self._check(lib().vadx_set_graph(self.h, 1 if on else 0))

@@ -231,10 +231,12 @@ def test_launch_shapes_are_bit_identical():
     b = inputs.grid_uneven(30, seed=9)
     cfg = inputs.RunConfig(n_steps=700, transient_steps=100, seed=2)
     outs = []
-    for mode, wg, item in ((1, 0, 0), (0, 0, 0), (0, 3, 96), (0, 1, 250)):
+    for mode, wg, item, waves in ((1, 0, 0, 2), (0, 0, 0, 2), (0, 3, 96, 2), (0, 1, 250, 2),
+                                  (0, 0, 0, 4), (0, 2, 500, 4)):
         sw = vadx.Sweep(0, gpu_model("literature-B"))
         ids = [sw.add_connectome(c) for c in conns]
         sw.ctx.vadx_set_launch(mode, wg, item)
+        sw.ctx.vadx_set_waves_per_simd(waves)
         sw.set_batch(b, conn_ids=ids)
         sw.plan(vadx.make_run(cfg))
         sw.integrate()
@@ -325,11 +327,13 @@ def test_autotuner_choice_cached_and_result_unchanged(tmp_path):
     sw.set_batch(b, conn_ids=ids)
     sw.plan(vadx.make_run(cfg))
     cache = str(tmp_path / "tune.json")
-    lanes, items = sw.autotune(cache, trial_steps=200)
+    lanes, items, waves = sw.autotune(cache, trial_steps=200)
     assert 200 <= lanes <= 512 and lanes % 64 == 0 and items in (250, 1000, 4000)
+    assert waves in (2, 4)
     entries = json.load(open(cache))
     assert len(entries) == 1 and list(entries.values())[0]["lanes"] == lanes
-    assert sw.autotune(cache, trial_steps=200) == (lanes, items)
+    assert list(entries.values())[0]["waves_per_simd"] == waves
+    assert sw.autotune(cache, trial_steps=200) == (lanes, items, waves)
     sw.integrate()
     sw.sync()
     for i in range(len(b)):
