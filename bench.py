@@ -35,8 +35,10 @@ def parse():
     p.add_argument("--workload", choices=["uniform", "uneven", "small"], default="uniform")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch shape instead of tuning it first")
-    p.add_argument("--waves-per-simd", type=int, default=2, choices=[2, 4],
+    p.add_argument("--waves-per-simd", type=int, default=2, choices=[2, 3, 4],
                    help="register budget of the integration kernel when not autotuning")
+    p.add_argument("--wg-instances", type=int, default=0,
+                   help="instances per workgroup when not autotuning (0 = as many as fit 512 lanes)")
     p.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "vadx_tune.json"))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-instances", type=int, default=64)
@@ -129,11 +131,12 @@ def main():
     run = vadx.make_run(cfg)
     sw.plan(run)
     sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
+    sw.ctx.vadx_set_launch(0, args.wg_instances, 0)
     sw.plan(run)
-    shape = {"lanes_per_workgroup": 512, "item_steps": 1000, "waves_per_simd": args.waves_per_simd,
-             "autotuned": False}
+    shape = {"instances_per_workgroup": args.wg_instances or "max", "item_steps": 1000,
+             "waves_per_simd": args.waves_per_simd, "autotuned": False}
     if not args.no_autotune:
-        lanes, items, waves = sw.autotune(args.tune_cache)
+        lanes, items, waves = sw.autotune(args.tune_cache, trial_steps=5000)
         shape = {"lanes_per_workgroup": lanes, "item_steps": items, "waves_per_simd": waves,
                  "autotuned": True}
     ctx = sw.ctx

@@ -277,7 +277,9 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 // until the queue is empty. The wait is bounded: on timeout the kernel
 // records an error and the workgroup stops.
 // OCC: waves per SIMD the register allocation must allow (2: one 512-lane
-// workgroup per CU; 4: two, at the price of a few register spills per step).
+// workgroup per CU, no spills; 3: two 384-lane or three 256-lane workgroups,
+// a few spills outside the step loop; 4: two 512-lane workgroups, a few
+// spills per step).
 template <int B, bool EQ, int OCC>
 __global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
 {
@@ -389,6 +391,9 @@ hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_thre
     if (occ == 4)
         return eq ? launch_integrate_eq<true, 4>(a, n_groups, block_threads, q, grid, s)
                   : launch_integrate_eq<false, 4>(a, n_groups, block_threads, q, grid, s);
+    if (occ == 3)
+        return eq ? launch_integrate_eq<true, 3>(a, n_groups, block_threads, q, grid, s)
+                  : launch_integrate_eq<false, 3>(a, n_groups, block_threads, q, grid, s);
     return eq ? launch_integrate_eq<true, 2>(a, n_groups, block_threads, q, grid, s)
               : launch_integrate_eq<false, 2>(a, n_groups, block_threads, q, grid, s);
 }
@@ -422,7 +427,9 @@ template <int OCC> static int resident(int block, int block_threads)
 
 int persistent_blocks_per_cu(int block, int block_threads, int occ)
 {
-    return occ == 4 ? resident<4>(block, block_threads) : resident<2>(block, block_threads);
+    if (occ == 4) return resident<4>(block, block_threads);
+    if (occ == 3) return resident<3>(block, block_threads);
+    return resident<2>(block, block_threads);
 }
 
 // ------------------------------------------------------------------ FC and statistics

@@ -663,7 +663,7 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
 vadx_status vadx_set_waves_per_simd(vadx_ctx *c, int32_t waves)
 {
     if (!c) return VADX_E_ARG;
-    if (waves != 0 && waves != 2 && waves != 4) return fail(c, VADX_E_ARG, "waves per SIMD must be 2 or 4");
+    if (waves != 0 && (waves < 2 || waves > 4)) return fail(c, VADX_E_ARG, "waves per SIMD must be 2, 3 or 4");
     c->occ = waves == 0 ? 2 : waves;
     c->planned = false;
     return VADX_OK;
@@ -861,7 +861,7 @@ static bool tune_lookup(const char *path, const std::string &key, int *lanes, in
         if (std::sscanf(line.c_str() + pl + 8, "%d", &l) == 1 &&
             std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 &&
             std::sscanf(line.c_str() + pw + 17, "%d", &w) == 1 && l >= 64 && l <= 512 && it > 0 &&
-            (w == 2 || w == 4)) {
+            w >= 2 && w <= 4) {
             *lanes = l;
             *items = it;
             *occ = w;
@@ -988,7 +988,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
                 }
             }
             if (same) continue;
-            for (int w : {2, 4}) {
+            for (int w : {2, 3, 4}) {
                 if (result) break;
                 result = trial(l, 1000, w, &ms);
                 if (result == VADX_OK && (best_ms < 0 || ms < best_ms)) {

@@ -10,7 +10,11 @@ The plain method simulates every point of a dense grid. The guided sweep
   4. simulates the points of largest gradient plus a random audit sample,
      each with the noise stream it has in the plain sweep (its grid index as
      noise key), so a refined point carries exactly its plain-sweep value,
-  5. keeps the predictions elsewhere.
+  5. uses the audit sample -- simulated points drawn independently of the
+     score -- to estimate, for each score threshold, the fraction of the grid
+     that would stay unrefined with an FC error above the bound, and refines
+     further down the score ranking until that estimate is below the target,
+  6. keeps the predictions elsewhere.
 The plain simulation stays the judge: the error of the guided result is
 measured against plain runs of a random sample of grid points (bit-identical
 to the full plain sweep at those points), and the plain sweep's time is the
@@ -54,6 +58,8 @@ class GuidedConfig:
     n_check: int = 4096                # grid points simulated plainly to measure the error
     chunk: int = 16384                 # instances per simulation launch
     err_bound: float = 0.05
+    target_exceed: float = 0.045       # audit estimate of the grid fraction above err_bound
+    adaptive: bool = True
 
 
 class Simulator:
@@ -129,24 +135,46 @@ def train_surrogate(X, Y, cfg: GuidedConfig, log=print):
                  "history": history}
 
 
-def screen(net, grid_X, cfg: GuidedConfig):
-    """Predicted statistics of every grid point and the selected indices."""
+def screen(net, grid_X):
+    """Predicted statistics of every grid point and the screening score
+    (device tensor)."""
     import torch
     t0 = time.perf_counter()
     Xd = _dev(grid_X)
     Y, _, score = net.predict(Xd, jacobian=False,
                               score_outputs=(STATS.index("sync_index"), STATS.index("fc_mean")))
-    n = grid_X.shape[0]
-    k = int(round(cfg.top_frac * n))
-    cap = k + int(n * cfg.audit_frac * 1.5) + 1024
-    sel = torch.empty(cap, dtype=torch.int64, device=Xd.device)
-    aud = torch.empty(cap, dtype=torch.uint8, device=Xd.device)
-    m = net.select(score, k, cfg.audit_frac, cfg.audit_seed, sel, aud)
     Yh = Y.cpu().numpy()
-    idx = sel[:m].cpu().numpy()
-    is_aud = aud[:m].cpu().numpy().astype(bool)
     torch.cuda.synchronize()
-    return Yh, idx, is_aud, time.perf_counter() - t0
+    return Yh, score, time.perf_counter() - t0
+
+
+def select(net, score, k, cfg: GuidedConfig):
+    """Indices of the k largest scores plus the audit sample, and audit flags."""
+    import torch
+    n = score.numel()
+    cap = k + int(n * cfg.audit_frac * 1.5) + 1024
+    sel = torch.empty(cap, dtype=torch.int64, device=score.device)
+    aud = torch.empty(cap, dtype=torch.uint8, device=score.device)
+    m = net.select(score, k, cfg.audit_frac, cfg.audit_seed, sel, aud)
+    return sel[:m].cpu().numpy(), aud[:m].cpu().numpy().astype(bool)
+
+
+def refined_count(score_aud, err_aud, k1, n, bound, target):
+    """Number k2 >= k1 of top-score points to simulate so that the grid points
+    left unrefined with an error above `bound` are estimated to be at most a
+    fraction `target` of the grid. The audit points are an independent random
+    sample of the points outside the top k1 (each taken with the same
+    probability), so the audit point ranked j by score stands for
+    (n - k1) / len(audit) grid points, and the bad audit points ranked below it
+    estimate the bad grid points a cut there would leave."""
+    m = len(err_aud)
+    order = np.argsort(-score_aud, kind="stable")
+    bad = (err_aud[order] > bound).astype(np.int64)
+    # bad_after[j] = bad audit points ranked j and below
+    bad_after = np.concatenate([np.cumsum(bad[::-1])[::-1], [0]])
+    per_audit = (n - k1) / m
+    j = int(np.nonzero(bad_after * per_audit <= target * n)[0][0])
+    return min(n, k1 + int(np.ceil(j * per_audit)))
 
 
 def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False):
@@ -161,15 +189,41 @@ def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False
     train = inputs.sample_box(cfg.n_train, seed=cfg.train_seed)
     Ytrain, ftrain, t_data = sim(train, TRAIN_KEY_BASE + np.arange(cfg.n_train), "training set")
     net, tinfo = train_surrogate(_points(train), Ytrain, cfg, log)
-    Yhat, idx, is_aud, t_screen = screen(net, G, cfg)
+    Yhat, score, t_screen = screen(net, G)
+    t0 = time.perf_counter()
+    k1 = int(round(cfg.top_frac * n))
+    idx, is_aud = select(net, score, k1, cfg)
+    t_select = time.perf_counter() - t0
     log(f"[guided] screened {n} points in {t_screen:.2f} s; refining {len(idx)} "
         f"({int((~is_aud).sum())} by gradient, {int(is_aud.sum())} audit)")
     Yref, fref, t_refine = sim(grid.subset(idx), idx, "refinement")
+    fc = STATS.index("fc_mean")
+    k2 = k1
+    if cfg.adaptive and is_aud.any():
+        t0 = time.perf_counter()
+        aud = idx[is_aud]
+        err_aud = np.abs(Yhat[aud, fc] - Yref[is_aud, fc])
+        k2 = refined_count(score[aud].cpu().numpy(), err_aud, k1, n, cfg.err_bound,
+                           cfg.target_exceed)
+        if k2 > k1:
+            idx2, is_aud2 = select(net, score, k2, cfg)
+            new = np.setdiff1d(idx2, idx, assume_unique=True)
+            t_select += time.perf_counter() - t0
+            log(f"[guided] audit: {int((err_aud > cfg.err_bound).sum())}/{len(aud)} audit points "
+                f"above {cfg.err_bound}; refining the top {k2 / n:.1%} ({len(new)} more runs)")
+            Ynew, fnew, t_more = sim(grid.subset(new), new, "refinement, second pass")
+            t_refine += t_more
+            idx = np.concatenate([idx, new])
+            Yref = np.concatenate([Yref, Ynew])
+            fref = np.concatenate([fref, fnew])
+            is_aud = np.concatenate([is_aud, np.zeros(len(new), bool)])
+        else:
+            t_select += time.perf_counter() - t0
     guided = Yhat.copy()
     guided[idx] = Yref
     refined = np.zeros(n, bool)
     refined[idx] = True
-    t_guided = t_data + tinfo["seconds"] + t_screen + t_refine
+    t_guided = t_data + tinfo["seconds"] + t_screen + t_select + t_refine
 
     if plain_full:
         chk = np.arange(n)
@@ -193,8 +247,9 @@ def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False
         "fc_mean_err": errs(STATS.index("fc_mean")),
         "fc_sc_corr_err": errs(STATS.index("fc_sc_corr")),
         "sync_index_err": errs(STATS.index("sync_index")),
+        "top_fraction_refined": k2 / n,
         "seconds": {"train_data": t_data, "train": tinfo["seconds"], "screen": t_screen,
-                    "refine": t_refine, "guided_total": t_guided,
+                    "select": t_select, "refine": t_refine, "guided_total": t_guided,
                     "plain": t_plain, "plain_is_extrapolated": not plain_full,
                     "plain_sec_per_instance": sec_per_inst},
         "time_ratio_guided_over_plain": t_guided / t_plain,

@@ -10,7 +10,10 @@ the unperturbed one by more than 1e-7 on the same scale (an amplification of
 well-conditioned cases the horizon covers the whole window and the test
 requires it to. FC: within 0.02 absolute over long runs where the run is
 predictable; where the FP64 model is itself chaotic, within 0.02 plus twice the
-FC spread that the 1e-9 perturbation alone produces.
+FC spread of an FP64 ensemble whose members start from initial rates changed
+by 1e-9 and by single-precision rounding amounts (6e-8 and 2.4e-7 relative):
+the single-precision drift perturbs the trajectory by that much every step,
+so only an ensemble of such perturbations spans the realisations it may take.
 """
 import os
 
@@ -25,7 +28,7 @@ TOL_STATE = 1e-4
 TOL_FC = 0.02
 PERT = 1e-9
 HORIZON_TOL = 1e-7
-ENSEMBLE = (0.0, 1e-9, 2e-9, -1e-9, 3e-9, -2e-9)
+ENSEMBLE = (0.0, 1e-9, -1e-9, 6e-8, -6e-8, 2.4e-7)
 NTHREADS = min(16, os.cpu_count() or 1)
 
 
@@ -232,7 +235,7 @@ def test_launch_shapes_are_bit_identical():
     cfg = inputs.RunConfig(n_steps=700, transient_steps=100, seed=2)
     outs = []
     for mode, wg, item, waves in ((1, 0, 0, 2), (0, 0, 0, 2), (0, 3, 96, 2), (0, 1, 250, 2),
-                                  (0, 0, 0, 4), (0, 2, 500, 4)):
+                                  (0, 0, 0, 4), (0, 2, 500, 4), (0, 5, 0, 3)):
         sw = vadx.Sweep(0, gpu_model("literature-B"))
         ids = [sw.add_connectome(c) for c in conns]
         sw.ctx.vadx_set_launch(mode, wg, item)
@@ -329,7 +332,7 @@ def test_autotuner_choice_cached_and_result_unchanged(tmp_path):
     cache = str(tmp_path / "tune.json")
     lanes, items, waves = sw.autotune(cache, trial_steps=200)
     assert 200 <= lanes <= 512 and lanes % 64 == 0 and items in (250, 1000, 4000)
-    assert waves in (2, 4)
+    assert waves in (2, 3, 4)
     entries = json.load(open(cache))
     assert len(entries) == 1 and list(entries.values())[0]["lanes"] == lanes
     assert list(entries.values())[0]["waves_per_simd"] == waves
