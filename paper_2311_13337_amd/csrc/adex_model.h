@@ -54,7 +54,17 @@ struct KModel {
     float cF[2][2];             // cF[pop][0 = exc input, 1 = inh input]
     float inv_tauOU;
     float w_noise, rate_max, x_floor;
+    int same_inputs;            // both populations see the same (xe, xi): cF_ee = cF_ie, cF_ei = cF_ii
 };
+
+// Model variant of an instantiation of the step: bit 0 when tau_e == tau_i
+// (one d_s, tau_V a function of G alone), bit 1 when both populations see the
+// same inputs (the G-dependent parts of their transfer functions coincide).
+enum { kVarEq = 1, kVarSame = 2 };
+inline int model_variant(const KModel &M)
+{
+    return (M.tau_e == M.tau_i ? kVarEq : 0) | (M.same_inputs ? kVarSame : 0);
+}
 
 // A value with its gradient (a = d/dxe, b = d/dxi) and Hessian.
 template <class T> struct Jet { T v, a, b, aa, ab, bb; };
@@ -204,13 +214,40 @@ template <class T> VADX_HD void erfc_and_gauss(T z, T &g, T &e)
 // Transfer function of population `pop` with its value and derivatives in
 // (xe, xi). Also returns mu_V (value) for the adaptation equation.
 // EQ: tau_e == tau_i, so d_i = d_e, 1/tau_V = d_e and sigma_V^2 = (A_e + A_i) d_e / 2.
+// The parts of the transfer function that depend on the inputs only through
+// xe, xi and G = g_L + a_e xe + a_i xi, not on the population: shared by the
+// two populations when their inputs coincide.
+template <class T> struct TFShared {
+    T xe, xi, r, r2, r3;
+    T de, he1, he2;             // d_e = 1/(C_m/G + tau_e) and its first two derivatives in G
+    T cexe, cixi;               // c_e xe, c_i xi
+};
+
+template <class T> VADX_HD TFShared<T> tf_shared(const KModel &M, T xe, T xi)
+{
+    TFShared<T> g;
+    g.xe = xe;
+    g.xi = xi;
+    T G = fmaf_(T(M.aE), xe, fmaf_(T(M.aI), xi, T(M.gL)));
+    g.r = rcp(G);
+    g.r2 = g.r * g.r;
+    g.r3 = g.r2 * g.r;
+    // d_s = 1/(C_m/G + tau_s) = G/(C_m + tau_s G): h' = C_m (d r)^2, h'' = -2 tau_s C_m (d r)^3
+    g.de = rcp(fmaf_(T(M.Cm), g.r, T(M.tau_e)));
+    T qe = g.de * g.r;
+    g.he1 = T(M.Cm) * qe * qe;
+    g.he2 = T(-2) * T(M.tau_e) * g.he1 * qe;
+    g.cexe = T(M.ce) * xe;
+    g.cixi = T(M.ci) * xi;
+    return g;
+}
+
 template <bool EQ, class T>
-VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
+VADX_HD Jet<T> transfer(const KModel &M, int pop, const TFShared<T> &g, T W, T &muV_out)
 {
     const T aE = T(M.aE), aI = T(M.aI);
-    T G = fmaf_(aE, xe, fmaf_(aI, xi, T(M.gL)));
-    T r = rcp(G);
-    T r2 = r * r, r3 = r2 * r;
+    const T xe = g.xe, xi = g.xi, r = g.r, r2 = g.r2, r3 = g.r3;
+    const T de = g.de, he1 = g.he1, he2 = g.he2;
     // mu_V through A = (E_e - mu_V) G = alpha_e + beta_e xi (linear in xi) and
     // B = (E_i - mu_V) G = alpha_i + beta_i xe (linear in xe): mu_V = E_e - A/G
     T c0 = T(M.gLEL[pop]) - W;
@@ -230,7 +267,7 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
     // Pi = c_e xe A^2 + c_i xi B^2 (c_s = K_s tau_s^2 Q_s^2), whose derivatives
     // are exact polynomials
     const T ce = T(M.ce), ci = T(M.ci);
-    T cexe = ce * xe, cixi = ci * xi;
+    const T cexe = g.cexe, cixi = g.cixi;
     T A2 = A * A, B2 = B * B;
     Jet<T> PI;
     PI.v = fmaf_(cexe, A2, cixi * B2);
@@ -239,11 +276,6 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
     PI.aa = T(M.ci2bI2) * xi;
     PI.ab = fmaf_(T(M.ce2bE), A, T(M.ci2bI) * B);
     PI.bb = T(M.ce2bE2) * xe;
-    // d_s = 1/(C_m/G + tau_s) = G/(C_m + tau_s G): h' = C_m (d r)^2, h'' = -2 tau_s C_m (d r)^3
-    T de = rcp(fmaf_(T(M.Cm), r, T(M.tau_e)));
-    T qe = de * r;
-    T he1 = T(M.Cm) * qe * qe;
-    const T he2 = T(-2) * T(M.tau_e) * he1 * qe;
     Jet<T> S2, ITV, TV;                              // 2 sigma_V^2, 1/tau_V, tau_V
     if constexpr (EQ) {
         // S2 = Pi phi(G), phi = d_e / G^4: (ln phi)' = -(3 + tau d_e)/G,
@@ -324,11 +356,11 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
     V.bb = fmaf_(u0, MU.bb, fmaf_(k1, SQ.bb, fmaf_(k2, TV.bb,
            fmaf_(wb0, MU.b, fmaf_(wb1, SQ.b, wb2 * TV.b)))));
     Jet<T> Z = jmul(V, Q);                            // (V_thre - mu_V)/(sqrt2 sigma_V)
-    T g, e;
-    erfc_and_gauss(Z.v, g, e);
+    T ez, e;
+    erfc_and_gauss(Z.v, ez, e);
     // F = erfc(Z) / (2 tau_V): the factor 1/2 rides on erfc's chain coefficients
     T g1 = T(-0.5f * 1.1283791670955126f) * e;
-    Jet<T> GZ = jchain(Z, T(0.5f) * g, g1, T(-2) * Z.v * g1);
+    Jet<T> GZ = jchain(Z, T(0.5f) * ez, g1, T(-2) * Z.v * g1);
     return jmul(GZ, ITV);
 }
 
@@ -336,7 +368,7 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, T xe, T xi, T W, T &muV_out)
 template <class T> struct InstParams { T S, b_e, a_e; };
 
 // Drift of one region's 8 states given its coupling input c (eq. 1-4).
-template <bool EQ, class T>
+template <int VAR, class T>
 VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
 {
     const T E = X[0], I = X[1], Cee = X[2], Cei = X[3], Cii = X[4];
@@ -346,8 +378,18 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
     T xe1 = maxf_(exc + T(M.cF[1][0]), T(M.x_floor));
     T xi1 = maxf_(I + T(M.cF[1][1]), T(M.x_floor));
     T muVe, muVi;
-    Jet<T> Fe = transfer<EQ>(M, 0, xe0, xi0, X[5], muVe);
-    Jet<T> Fi = transfer<EQ>(M, 1, xe1, xi1, X[6], muVi);
+    const TFShared<T> g0 = tf_shared(M, xe0, xi0);
+    constexpr bool EQ = (VAR & kVarEq) != 0;
+    Jet<T> Fe = transfer<EQ>(M, 0, g0, X[5], muVe);
+    Jet<T> Fi;
+    if constexpr ((VAR & kVarSame) != 0) {
+        (void)xe1;
+        (void)xi1;
+        Fi = transfer<EQ>(M, 1, g0, X[6], muVi);
+    } else {
+        const TFShared<T> g1 = tf_shared(M, xe1, xi1);
+        Fi = transfer<EQ>(M, 1, g1, X[6], muVi);
+    }
     const T iT = T(M.invT);
     T fe = Fe.v - E, fi = Fi.v - I;
     // eq. 1: T dnu/dt = (F - nu) + 1/2 C_ee F_ee + C_ei F_ei + 1/2 C_ii F_ii
@@ -395,13 +437,13 @@ template <class T> VADX_HD bool project(const KModel &M, T X[8])
 // in S (double), so the rounding of the state does not build up over the
 // run. gdw is the OU increment (sigma/tau_OU) sqrt(dt) z. Returns true when a
 // bound was hit.
-template <bool EQ, class T, class S>
+template <int VAR, class T, class S>
 VADX_HD bool step_region(const KModel &M, int integrator, S dt, S X[8], T c, T be, T ae, S gdw)
 {
     T xf[8], f0[8], f1[8];
     S Xt[8];
     for (int q = 0; q < 8; ++q) xf[q] = T(X[q]);
-    drift<EQ>(M, xf, c, be, ae, f0);
+    drift<VAR>(M, xf, c, be, ae, f0);
     if (integrator == 1) {
         for (int q = 0; q < 8; ++q) X[q] = X[q] + dt * S(f0[q]);
         X[7] = X[7] + gdw;
@@ -411,7 +453,7 @@ VADX_HD bool step_region(const KModel &M, int integrator, S dt, S X[8], T c, T b
     Xt[7] = Xt[7] + gdw;
     bool hit = project(M, Xt);
     for (int q = 0; q < 8; ++q) xf[q] = T(Xt[q]);
-    drift<EQ>(M, xf, c, be, ae, f1);
+    drift<VAR>(M, xf, c, be, ae, f1);
     const S hdt = S(0.5) * dt;
     for (int q = 0; q < 8; ++q) X[q] = X[q] + hdt * (S(f0[q]) + S(f1[q]));
     X[7] = X[7] + gdw;

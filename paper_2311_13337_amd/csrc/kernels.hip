@@ -122,7 +122,7 @@ __device__ __forceinline__ void normals4(uint32_t seed, uint32_t id, uint32_t q,
 // Ring row of region j: D slots holding E_j at steps n mod D, followed by
 // B - 1 mirror slots (slot D + s repeats slot s), so the B consecutive
 // history values a block needs from one edge never wrap.
-template <int B, bool EQ>
+template <int B, int VAR>
 __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const GroupDev g,
                                                 int64_t n_begin, int64_t n_end, float *cbuf)
 {
@@ -223,7 +223,7 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                     normals4(a.seed, I.id, (uint32_t)(n >> 2), (uint32_t)k, z4);
                 const float z = r == 0 ? z4[0] : (r == 1 ? z4[1] : (r == 2 ? z4[2] : z4[3]));
                 const float c = cbuf[b * nthr + tid];
-                bool hit = step_region<EQ>(a.M, a.integrator, a.dt, X, c, be, ae,
+                bool hit = step_region<VAR>(a.M, a.integrator, a.dt, X, c, be, ae,
                                            a.gdw_scale * (double)z);
                 double chk = ((X[0] + X[1]) + (X[2] + X[3])) + ((X[4] + X[5]) + (X[6] + X[7]));
                 fl |= hit ? 2u : 0u;
@@ -263,11 +263,11 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
     }
 }
 
-template <int B, bool EQ>
+template <int B, int VAR>
 __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 {
     extern __shared__ float cbuf[];   // [B][blockDim.x] coupling of the block's steps
-    integrate_group<B, EQ>(a, a.groups[blockIdx.x], a.n_begin, a.n_end, cbuf);
+    integrate_group<B, VAR>(a, a.groups[blockIdx.x], a.n_begin, a.n_end, cbuf);
 }
 
 // Persistent form: workgroups pull (group, chunk) items from a queue in
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 // workgroup per CU, no spills; 3: two 384-lane or three 256-lane workgroups,
 // a few spills outside the step loop; 4: two 512-lane workgroups, a few
 // spills per step).
-template <int B, bool EQ, int OCC>
+template <int B, int VAR, int OCC>
 __global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
 {
     extern __shared__ float cbuf[];
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(Integrat
         }
         const int64_t nb = a.n_begin + (int64_t)c * q.item_steps;
         const int64_t ne = nb + q.item_steps < a.n_end ? nb + q.item_steps : a.n_end;
-        integrate_group<B, EQ>(a, a.groups[gi], nb, ne, cbuf);
+        integrate_group<B, VAR>(a, a.groups[gi], nb, ne, cbuf);
         __threadfence();                           // publish state and history
         __syncthreads();
         if (tid == 0)
@@ -353,64 +353,72 @@ __global__ void queue_reset_kernel(QueueArgs q)
     if (i < q.n_groups) q.done[i] = 0;
 }
 
-template <int B, bool EQ, int OCC>
+template <int B, int VAR, int OCC>
 static hipError_t launch_integrate_b(const IntegrateArgs &a, int n_groups, int block_threads,
                                      const QueueArgs *q, int grid, hipStream_t s)
 {
     size_t lds = (size_t)B * block_threads * sizeof(float);
     if (q == nullptr) {
-        hipLaunchKernelGGL((integrate_kernel<B, EQ>), dim3(n_groups), dim3(block_threads), lds, s, a);
+        hipLaunchKernelGGL((integrate_kernel<B, VAR>), dim3(n_groups), dim3(block_threads), lds, s, a);
     } else {
         hipLaunchKernelGGL(queue_reset_kernel, dim3((q->n_groups + 255) / 256), dim3(256), 0, s, *q);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((integrate_persistent_kernel<B, EQ, OCC>), dim3(grid), dim3(block_threads),
+        hipLaunchKernelGGL((integrate_persistent_kernel<B, VAR, OCC>), dim3(grid), dim3(block_threads),
                            lds, s, a, *q);
     }
     return hipGetLastError();
 }
 
-template <bool EQ, int OCC>
-static hipError_t launch_integrate_eq(const IntegrateArgs &a, int n_groups, int block_threads,
+template <int VAR, int OCC>
+static hipError_t launch_integrate_v(const IntegrateArgs &a, int n_groups, int block_threads,
                                       const QueueArgs *q, int grid, hipStream_t s)
 {
     switch (a.block) {
-    case 1: return launch_integrate_b<1, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 2: return launch_integrate_b<2, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 4: return launch_integrate_b<4, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 8: return launch_integrate_b<8, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 16: return launch_integrate_b<16, EQ, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 1: return launch_integrate_b<1, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 2: return launch_integrate_b<2, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 4: return launch_integrate_b<4, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 8: return launch_integrate_b<8, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 16: return launch_integrate_b<16, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+template <int OCC>
+static hipError_t launch_integrate_o(const IntegrateArgs &a, int n_groups, int block_threads,
+                                     const QueueArgs *q, int grid, hipStream_t s)
+{
+    switch (model_variant(a.M)) {
+    case 0: return launch_integrate_v<0, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 1: return launch_integrate_v<1, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 2: return launch_integrate_v<2, OCC>(a, n_groups, block_threads, q, grid, s);
+    default: return launch_integrate_v<3, OCC>(a, n_groups, block_threads, q, grid, s);
     }
 }
 
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
                             const QueueArgs *q, int grid, int occ, hipStream_t s)
 {
-    const bool eq = a.M.tau_e == a.M.tau_i;
-    if (occ == 4)
-        return eq ? launch_integrate_eq<true, 4>(a, n_groups, block_threads, q, grid, s)
-                  : launch_integrate_eq<false, 4>(a, n_groups, block_threads, q, grid, s);
-    if (occ == 3)
-        return eq ? launch_integrate_eq<true, 3>(a, n_groups, block_threads, q, grid, s)
-                  : launch_integrate_eq<false, 3>(a, n_groups, block_threads, q, grid, s);
-    return eq ? launch_integrate_eq<true, 2>(a, n_groups, block_threads, q, grid, s)
-              : launch_integrate_eq<false, 2>(a, n_groups, block_threads, q, grid, s);
+    if (occ == 4) return launch_integrate_o<4>(a, n_groups, block_threads, q, grid, s);
+    if (occ == 3) return launch_integrate_o<3>(a, n_groups, block_threads, q, grid, s);
+    return launch_integrate_o<2>(a, n_groups, block_threads, q, grid, s);
 }
 
 template <int B, int OCC> static int resident_b(int block_threads)
 {
-    // both model variants have the same launch bounds and LDS use
-    int per_cu = 0;
+    // all model variants have the same launch bounds and LDS use
+    int per_cu = 1 << 30;
     size_t lds = (size_t)B * block_threads * sizeof(float);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_persistent_kernel<B, true, OCC>,
-                                                     block_threads, lds) != hipSuccess)
-        return 0;
-    int per_cu2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, integrate_persistent_kernel<B, false, OCC>,
-                                                     block_threads, lds) != hipSuccess)
-        return 0;
-    return per_cu < per_cu2 ? per_cu : per_cu2;
+    void (*kernels[4])(IntegrateArgs, QueueArgs) = {
+        integrate_persistent_kernel<B, 0, OCC>, integrate_persistent_kernel<B, 1, OCC>,
+        integrate_persistent_kernel<B, 2, OCC>, integrate_persistent_kernel<B, 3, OCC>};
+    for (auto k : kernels) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_threads, lds) != hipSuccess)
+            return 0;
+        per_cu = n < per_cu ? n : per_cu;
+    }
+    return per_cu;
 }
 
 template <int OCC> static int resident(int block, int block_threads)

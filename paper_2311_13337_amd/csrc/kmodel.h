@@ -55,6 +55,7 @@ inline KModel make_kmodel(const vadx_model &m)
     k.b_i = (float)m.b_i; k.a_i = (float)m.a_i;
     k.cF[0][0] = (float)m.cF_ee; k.cF[0][1] = (float)m.cF_ei;
     k.cF[1][0] = (float)m.cF_ie; k.cF[1][1] = (float)m.cF_ii;
+    k.same_inputs = k.cF[0][0] == k.cF[1][0] && k.cF[0][1] == k.cF[1][1];
     k.inv_tauOU = (float)(1.0 / m.tau_OU);
     k.w_noise = (float)m.w_noise; k.rate_max = (float)m.rate_max; k.x_floor = (float)m.x_floor;
     return k;
