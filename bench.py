@@ -140,6 +140,7 @@ def main():
         shape = {"lanes_per_workgroup": lanes, "item_steps": items, "waves_per_simd": waves,
                  "autotuned": True}
     ctx = sw.ctx
+    shape.update(ctx.vadx_launch_info())
     for _ in range(args.warmup):
         sw.integrate()
     torch.cuda.synchronize()
@@ -173,12 +174,14 @@ def main():
     rs_per_launch = region_total * cfg.n_steps / launches_per_step
     launch_ms = ms_int / n_int
     achieved = flop_rs * rs_per_launch / (launch_ms / 1000.0) / 1e12
+    # HBM bytes of the integration kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
+    # (copy-calibrated), stored per region-step for this kernel source
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
         if tj.get("workload") == args.workload and tj.get("kernel_source_sha") == _src_sha():
-            traffic = tj.get("bytes_per_launch")
+            traffic = round(tj["bytes_per_region_step"] * rs_per_launch)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
             "traffic": traffic,
@@ -206,7 +209,7 @@ def main():
 def _src_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "adex_model.h", "engine.h"):
+    for f in ("kernels.hip", "adex_model.h", "engine.h", "kmodel.h", "philox.h"):
         with open(os.path.join(ROOT, "paper_2311_13337_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -87,7 +87,8 @@ typedef struct vadx_run {
     uint32_t seed;
     int32_t integrator;   /* VADX_HEUN (default) or VADX_EULER */
     int32_t noise_off;
-    int32_t chunk_steps;  /* steps per kernel launch; 0 = library default */
+    int32_t chunk_steps;  /* steps per kernel launch; 0 = library default (the whole
+                             run with the persistent queue, 10000 otherwise) */
     double fc_min_std;    /* kHz; a region whose rate std over the samples is
                              below it is silent: zero variance and covariances,
                              FC row 0 (diagonal 1), VADX_FLAG_ZERO_VAR set */
@@ -210,6 +211,12 @@ vadx_status vadx_set_waves_per_simd(vadx_ctx *ctx, int32_t waves);
 vadx_status vadx_autotune(vadx_ctx *ctx, const vadx_run *run, void *ws, size_t ws_bytes,
                           const char *cache_path, int32_t trial_steps, int32_t *lanes,
                           int32_t *item_steps, int32_t *waves);
+
+/* Launch shape of the current plan: groups of instances, threads per
+ * workgroup, workgroups launched (the persistent grid, or the groups) and the
+ * steps per block between workgroup barriers. Each pointer nullable. */
+vadx_status vadx_launch_info(vadx_ctx *ctx, int32_t *groups, int32_t *block_threads,
+                             int32_t *grid, int32_t *steps_per_block);
 
 /* Graph replay: with on = 1, vadx_integrate records the whole run (flag
  * clears, integration launches, FC) once into a HIP graph and replays it on

@@ -114,6 +114,9 @@ VADX_HD float lg2(float x)
 #endif
 }
 VADX_HD double sqr(double x) { return __builtin_sqrt(x); }
+VADX_HD double maxd_(double a, double b) { return __builtin_fmax(a, b); }
+VADX_HD double mind_(double a, double b) { return __builtin_fmin(a, b); }
+VADX_HD bool finite_(float x) { return __builtin_isfinite(x); }
 VADX_HD float fmaf_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 VADX_HD float absf_(float x) { return __builtin_fabsf(x); }
 VADX_HD float selectf(bool c, float a, float b) { return c ? a : b; }
@@ -411,54 +414,60 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
 
 // Projection onto admissible states after each stage: rates in [0, rate_max],
 // variances in [0, nu (rate_max - nu)] (bound for a variable confined to
-// [0, rate_max] with mean nu), |C_ei| <= sqrt(C_ee C_ii). Comparisons are
-// written so that a NaN passes through. Returns true when a bound was hit.
-template <class T> VADX_HD T clampv(T x, T lo, T hi, bool &hit)
+// [0, rate_max] with mean nu), |C_ei| <= sqrt(C_ee C_ii). Returns true when a
+// bound was hit. (Non-finite values are detected on the drift, before they
+// reach the state.)
+template <class S> VADX_HD S clampv(S x, S lo, S hi, bool &hit)
 {
-    bool l = x < lo, h = x > hi;
-    hit = hit || l || h;
-    return l ? lo : (h ? hi : x);
+    S y = mind_(maxd_(x, lo), hi);
+    hit = hit || (y != x);
+    return y;
 }
-template <class T> VADX_HD bool project(const KModel &M, T X[8])
+template <class S> VADX_HD bool project(const KModel &M, S X[8])
 {
     bool hit = false;
-    const T rm = T(M.rate_max);
-    X[0] = clampv(X[0], T(0), rm, hit);
-    X[1] = clampv(X[1], T(0), rm, hit);
-    X[2] = clampv(X[2], T(0), X[0] * (rm - X[0]), hit);
-    X[4] = clampv(X[4], T(0), X[1] * (rm - X[1]), hit);
-    T cb = sqr(X[2] * X[4]);
+    const S rm = S(M.rate_max);
+    X[0] = clampv(X[0], S(0), rm, hit);
+    X[1] = clampv(X[1], S(0), rm, hit);
+    X[2] = clampv(X[2], S(0), X[0] * (rm - X[0]), hit);
+    X[4] = clampv(X[4], S(0), X[1] * (rm - X[1]), hit);
+    S cb = sqr(X[2] * X[4]);
     X[3] = clampv(X[3], -cb, cb, hit);
     return hit;
 }
 
+// Flags of one step: a bound of the projection was hit, the drift was not
+// finite (every state enters the rate drifts, so their sum carries any NaN).
+enum { kStepNonfinite = 1u, kStepClamp = 2u };
+
 // One step of stochastic Heun (or Euler-Maruyama) for one region. The drift
 // is evaluated in T (float); the state X and its increments are accumulated
 // in S (double), so the rounding of the state does not build up over the
-// run. gdw is the OU increment (sigma/tau_OU) sqrt(dt) z. Returns true when a
-// bound was hit.
+// run. gdw is the OU increment (sigma/tau_OU) sqrt(dt) z. Returns kStep* flags.
 template <int VAR, class T, class S>
-VADX_HD bool step_region(const KModel &M, int integrator, S dt, S X[8], T c, T be, T ae, S gdw)
+VADX_HD uint32_t step_region(const KModel &M, int integrator, S dt, S X[8], T c, T be, T ae, S gdw)
 {
     T xf[8], f0[8], f1[8];
     S Xt[8];
     for (int q = 0; q < 8; ++q) xf[q] = T(X[q]);
     drift<VAR>(M, xf, c, be, ae, f0);
     if (integrator == 1) {
+        const uint32_t nf = finite_(f0[0] + f0[1]) ? 0u : kStepNonfinite;
         for (int q = 0; q < 8; ++q) X[q] = X[q] + dt * S(f0[q]);
         X[7] = X[7] + gdw;
-        return project(M, X);
+        return nf | (project(M, X) ? kStepClamp : 0u);
     }
     for (int q = 0; q < 8; ++q) Xt[q] = X[q] + dt * S(f0[q]);
     Xt[7] = Xt[7] + gdw;
     bool hit = project(M, Xt);
     for (int q = 0; q < 8; ++q) xf[q] = T(Xt[q]);
     drift<VAR>(M, xf, c, be, ae, f1);
+    const uint32_t nf = finite_((f0[0] + f0[1]) + (f1[0] + f1[1])) ? 0u : kStepNonfinite;
     const S hdt = S(0.5) * dt;
-    for (int q = 0; q < 8; ++q) X[q] = X[q] + hdt * (S(f0[q]) + S(f1[q]));
+    for (int q = 0; q < 8; ++q) X[q] = X[q] + hdt * S(f0[q] + f1[q]);
     X[7] = X[7] + gdw;
     hit = project(M, X) || hit;
-    return hit;
+    return nf | (hit ? kStepClamp : 0u);
 }
 
 } // namespace vadx

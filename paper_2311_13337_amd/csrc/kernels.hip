@@ -223,11 +223,8 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                     normals4(a.seed, I.id, (uint32_t)(n >> 2), (uint32_t)k, z4);
                 const float z = r == 0 ? z4[0] : (r == 1 ? z4[1] : (r == 2 ? z4[2] : z4[3]));
                 const float c = cbuf[b * nthr + tid];
-                bool hit = step_region<VAR>(a.M, a.integrator, a.dt, X, c, be, ae,
-                                           a.gdw_scale * (double)z);
-                double chk = ((X[0] + X[1]) + (X[2] + X[3])) + ((X[4] + X[5]) + (X[6] + X[7]));
-                fl |= hit ? 2u : 0u;
-                fl |= __builtin_isfinite(chk) ? 0u : 1u;
+                fl |= step_region<VAR>(a.M, a.integrator, a.dt, X, c, be, ae,
+                                       a.gdw_scale * (double)z);
                 // history of E: slot (n + 1) mod D, and its mirror
                 wm += 1;
                 wm -= (wm >= D) ? D : 0;

@@ -44,6 +44,10 @@ inline CF fmaf_(CF a, CF b, CF c) { CF::flop(2); return mk<float>(std::fma(a.v, 
 inline CF absf_(CF x) { return mk<float>(std::fabs(x.v)); }
 inline CF selectf(bool c, CF a, CF b) { return c ? a : b; }
 inline CF maxf_(CF a, CF b) { CF::flop(1); return mk<float>(std::fmax(a.v, b.v)); }
+inline CD maxd_(CD a, CD b) { CD::flop(1); return mk<double>(std::fmax(a.v, b.v)); }
+inline CD mind_(CD a, CD b) { CD::flop(1); return mk<double>(std::fmin(a.v, b.v)); }
+inline bool finite_(CF x) { return std::isfinite(x.v); }
+template <class U> bool operator!=(Cnt<U> a, Cnt<U> b) { return a.v != b.v; }
 } // namespace vadx
 
 #include "adex_model.h"

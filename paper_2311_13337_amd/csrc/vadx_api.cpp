@@ -567,7 +567,10 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     a.seed = r->seed;
     a.integrator = r->integrator;
     a.block = c->block;
-    int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps : 10000;
+    // default launch length: the whole run for the persistent queue (its only
+    // tail is then the end of the run), 10000 steps for one-workgroup-per-group
+    int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps
+                                       : (c->launch_mode == 0 ? std::max<int64_t>(r->n_steps, 1) : 10000);
     chunk = std::max<int64_t>(chunk / c->block, 1) * c->block;
     const int ng = (int)c->h_groups.size();
     QueueArgs q{};
@@ -666,6 +669,23 @@ vadx_status vadx_set_waves_per_simd(vadx_ctx *c, int32_t waves)
     if (waves != 0 && (waves < 2 || waves > 4)) return fail(c, VADX_E_ARG, "waves per SIMD must be 2, 3 or 4");
     c->occ = waves == 0 ? 2 : waves;
     c->planned = false;
+    return VADX_OK;
+}
+
+vadx_status vadx_launch_info(vadx_ctx *c, int32_t *groups, int32_t *block_threads,
+                             int32_t *grid, int32_t *steps_per_block)
+{
+    if (!c) return VADX_E_ARG;
+    if (!c->planned) return fail(c, VADX_E_STATE, "no plan");
+    int g = (int)c->h_groups.size();
+    if (c->launch_mode == 0) {
+        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads, c->occ);
+        g = std::min(g, per_cu * c->cus);
+    }
+    if (groups) *groups = (int32_t)c->h_groups.size();
+    if (block_threads) *block_threads = c->wg_threads;
+    if (grid) *grid = g;
+    if (steps_per_block) *steps_per_block = c->block;
     return VADX_OK;
 }
 

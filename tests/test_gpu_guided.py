@@ -73,33 +73,38 @@ def test_select_matches_definition(n, k, frac, ties):
 
 
 def test_guided_sweep_small_grid():
-    """12^4 grid, 1 s runs: guided = 2048 training runs + 6% of the grid
-    simulated; the error against the plain sweep is measured at every point,
-    refined points reproduce their plain values exactly, and the guided error
-    is compared with what the same simulation budget gives without the
-    network (nearest simulated training point)."""
+    """12^4 grid with 10-s runs (4096 training runs): the whole grid is also
+    simulated plainly, so the error is exact. The guided result meets the
+    error bound, its refined points are the plain runs, it costs less than the
+    plain sweep, and it beats the same number of simulations spent without
+    the network (random grid points, each other point taking the value of its
+    nearest simulated point)."""
     from paper_2311_13337_amd import guided, inputs
-    cfg = guided.GuidedConfig(grid_res=12, n_train=2048,
-                              run=inputs.RunConfig(n_steps=10000, transient_steps=2000),
-                              max_epochs=300, patience=40, chunk=8192)
+    cfg = guided.GuidedConfig(grid_res=12, n_train=4096,
+                              run=inputs.RunConfig(n_steps=100000, transient_steps=10000),
+                              max_epochs=400, patience=40, chunk=16384)
     res, data = guided.guided_sweep(cfg, plain_full=True)
     print("[guided-small]", {k: v for k, v in res.items() if k != "train"}, flush=True)
     g, p, idx = data["guided"], data["plain"], data["idx"]
     assert np.array_equal(g[idx], p[idx])               # refined points are plain runs
-    assert res["refined"] < 0.08 * res["grid_points"]
-    # the network against no network at the same budget: predict each grid
-    # point by its nearest training point (normalised box distance)
+    assert res["fc_mean_err"]["p95"] < cfg.err_bound
+    assert res["time_ratio_guided_over_plain"] < 1.0
+    # the same simulation budget without the network
+    n = len(p)
+    budget = cfg.n_train + len(idx)
     lo = np.array([b[0] for b in guided.BOX], np.float32)
     hi = np.array([b[1] for b in guided.BOX], np.float32)
     G = (data["grid"] - lo) / (hi - lo)
-    Tn = (data["train_X"] - lo) / (hi - lo)
-    nn = np.empty(len(G), np.int64)
-    for c0 in range(0, len(G), 2048):
-        d2 = ((G[c0:c0 + 2048, None, :] - Tn[None, :, :]) ** 2).sum(-1)
-        nn[c0:c0 + 2048] = d2.argmin(1)
-    base = data["train_Y"][nn]
-    base[idx] = p[idx]
-    e_base = np.quantile(np.abs(base[:, 0] - p[:, 0]), 0.95)
-    print(f"[guided-small] fc_mean p95 error: guided {res['fc_mean_err']['p95']:.4f}, "
-          f"nearest-sample baseline {e_base:.4f}", flush=True)
-    assert res["fc_mean_err"]["p95"] < e_base
+    sim = np.sort(np.random.default_rng(2).choice(n, budget, replace=False))
+    nn = np.empty(n, np.int64)
+    for c0 in range(0, n, 2048):
+        d2 = ((G[c0:c0 + 2048, None, :] - G[None, sim, :]) ** 2).sum(-1)
+        nn[c0:c0 + 2048] = sim[d2.argmin(1)]
+    e_base = np.abs(p[nn, 0] - p[:, 0])
+    e_guided = np.abs(g[:, 0] - p[:, 0])
+    over_base = float((e_base > cfg.err_bound).mean())
+    over_guided = float((e_guided > cfg.err_bound).mean())
+    print(f"[guided-small] points above {cfg.err_bound}: guided {over_guided:.4f}, same budget "
+          f"without the network {over_base:.4f}; p95 {np.quantile(e_guided, 0.95):.4f} vs "
+          f"{np.quantile(e_base, 0.95):.4f}", flush=True)
+    assert over_guided < over_base
