@@ -444,6 +444,7 @@ int persistent_blocks_per_cu(int block, int block_threads, int occ)
 // through LDS in chunks of samples; covariance, Pearson FC, and the statistics.
 constexpr int kFcThreads = 256;
 constexpr int kFcLdsFloats = 8192;
+constexpr int kFcRegionsPerThread = 4;   // regions per thread in the moment sums (n <= 1024)
 
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
@@ -474,26 +475,19 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
     float *fc = a.ws + I.fc_off;
     const double inv_ns = ns > 0 ? 1.0 / (double)ns : 0.0;
 
-    // per-region moments
-    for (int k = tid; k < n; k += kFcThreads) {
-        double sh = ns > 0 ? (double)x[k] : 0.0, s1 = 0.0, s2 = 0.0;
-        for (int64_t s = 0; s < ns; ++s) {
-            double v = (double)x[s * n + k] - sh;
-            s1 += v;
-            s2 = fma(v, v, s2);
-        }
-        double m1 = s1 * inv_ns;
-        shift[k] = sh;
-        mean[k] = m1;   // mean of the shifted samples
-        const double vk = ns > 0 ? s2 * inv_ns - m1 * m1 : 0.0;
-        var[k] = vk < a.min_var ? 0.0 : vk;   // silent regions: zero variance
-    }
+    // shifts: the first sample of each region (exact in FP64)
+    for (int k = tid; k < n; k += kFcThreads) shift[k] = ns > 0 ? (double)x[k] : 0.0;
     __syncthreads();
 
     const int nT = (n + 3) / 4, npad = nT * 4;
     const int ntiles = nT * (nT + 1) / 2;
     const int chunk = kFcLdsFloats / npad;
     double s_f = 0, s_f2 = 0, s_w = 0, s_w2 = 0, s_fw = 0, s_cov = 0;
+    // per-region sums of the shifted samples and of their squares, gathered
+    // from the LDS-staged samples during the first pass over the tiles
+    double m1[kFcRegionsPerThread], m2[kFcRegionsPerThread];
+#pragma unroll
+    for (int q = 0; q < kFcRegionsPerThread; ++q) m1[q] = m2[q] = 0.0;
     for (int t0 = 0; t0 < ntiles; t0 += kFcThreads) {
         const int t = t0 + tid;
         int tr = 0, tcol = 0;
@@ -515,6 +509,20 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
                 xs[i] = k < n ? x[(s0 + s) * n + k] : 0.f;
             }
             __syncthreads();
+            if (t0 == 0) {
+#pragma unroll
+                for (int q = 0; q < kFcRegionsPerThread; ++q) {
+                    const int k = tid + q * kFcThreads;
+                    if (k < n) {
+                        const double sh = shift[k];
+                        for (int s = 0; s < cn; ++s) {
+                            const double v = (double)xs[s * npad + k] - sh;
+                            m1[q] += v;
+                            m2[q] = fma(v, v, m2[q]);
+                        }
+                    }
+                }
+            }
             if (t < ntiles) {
                 double sa[4], sb[4];
 #pragma unroll
@@ -537,6 +545,20 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
                         for (int j = 0; j < 4; ++j) P[i][j] = fma(va[i], vb[j], P[i][j]);
                 }
             }
+        }
+        if (t0 == 0) {
+            // moments complete: means of the shifted samples and variances
+#pragma unroll
+            for (int q = 0; q < kFcRegionsPerThread; ++q) {
+                const int k = tid + q * kFcThreads;
+                if (k < n) {
+                    const double mk = m1[q] * inv_ns;
+                    mean[k] = mk;
+                    const double vk = ns > 0 ? m2[q] * inv_ns - mk * mk : 0.0;
+                    var[k] = vk < a.min_var ? 0.0 : vk;   // silent regions: zero variance
+                }
+            }
+            __syncthreads();
         }
         if (t < ntiles) {
 #pragma unroll
