@@ -118,7 +118,9 @@ vadx_status vadx_set_model(vadx_ctx *ctx, const vadx_model *model);
  * [n*n] row-major (non-negative, zero diagonal) and tract lengths [n*n] in mm
  * (positive where w > 0). Weights are row-normalised on the device
  * (W_kj = w_kj / sum_j w_kj; all-zero rows stay zero); the raw w is the
- * structural connectivity used for the FC-SC correlation. 2 <= n <= 1024.
+ * structural connectivity used for the FC-SC correlation. 2 <= n <= 512 (one
+ * lane per region, an instance within one workgroup); larger n gives
+ * VADX_E_UNSUPPORTED.
  * *conn_id receives the index used by vadx_set_batch. */
 vadx_status vadx_add_connectome(vadx_ctx *ctx, int32_t n, const double *weights,
                                 const double *tract_mm, int32_t *conn_id);

@@ -245,7 +245,9 @@ vadx_status vadx_add_connectome(vadx_ctx *c, int32_t n, const double *w, const d
 {
     if (!c || !w || !len || !conn_id) return fail(c, VADX_E_ARG, "null argument");
     if (n < 2) return fail(c, VADX_E_ARG, "need at least 2 regions");
-    if (n > 1024) return fail(c, VADX_E_UNSUPPORTED, "at most 1024 regions per connectome");
+    if (n > 512)
+        return fail(c, VADX_E_UNSUPPORTED,
+                    "at most 512 regions per connectome (one lane per region, whole instances per workgroup)");
     HostConn hc;
     hc.n = n;
     int64_t nnz = 0;

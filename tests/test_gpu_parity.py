@@ -272,6 +272,24 @@ def test_mixed_region_counts_one_launch(oracle):
             check_trace(g, ref["trace"][q], pert["trace"][q], f"class {cls} instance {i}")
 
 
+def test_largest_region_count(oracle):
+    """512 regions (the largest a workgroup holds, ~102 edges per row): two
+    instances in their own workgroups, traced against the oracle."""
+    conn = inputs.synthetic_connectome(512, seed=6)
+    rng = np.random.default_rng(2)
+    batch = inputs._batch(rng.uniform(0, 0.2, 2), rng.uniform(0, 60, 2), rng.uniform(0, 4, 2),
+                          [4.0, 7.5])
+    cfg = inputs.RunConfig(n_steps=300, transient_steps=100, n_trace_steps=300, seed=7)
+    print("[parity] 512 regions, 2 instances x 300 steps", flush=True)
+    sw = run_gpu("literature-B", [conn], batch, cfg, trace=[0, 1])
+    assert sw.ctx.vadx_launch_info()["block_threads"] == 512
+    ref = run_oracle(oracle, "literature-B", conn, batch, cfg)
+    pert = run_oracle(oracle, "literature-B", conn, batch, cfg, perturb=True)
+    for i in range(2):
+        g = sw.ctx.vadx_read_trace(i, i, 300).astype(np.float64)
+        check_trace(g, ref["trace"][i], pert["trace"][i], f"512-region instance {i}")
+
+
 @pytest.mark.parametrize("integrator,noise_off", [(1, False), (0, True)])
 def test_euler_and_noise_free(oracle, integrator, noise_off):
     conn = inputs.synthetic_connectome(68)
@@ -429,6 +447,10 @@ def test_invalid_arguments_rejected():
         sw.ctx.vadx_add_connectome(w, conn.tract_mm)
     assert ei.value.status == vadx.VADX_E_ARG
     sw.add_connectome(conn)
+    big = inputs.synthetic_connectome(513, seed=4)
+    with pytest.raises(vadx.VadxError) as ei:
+        sw.ctx.vadx_add_connectome(big.weights, big.tract_mm)
+    assert ei.value.status == vadx.VADX_E_UNSUPPORTED
     with pytest.raises(vadx.VadxError):
         sw.ctx.vadx_set_batch([0.1], [np.nan], [0.0], [4.0])
     with pytest.raises(vadx.VadxError):
