@@ -35,7 +35,7 @@ def parse():
     p.add_argument("--workload", choices=["uniform", "uneven", "small"], default="uniform")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch shape instead of tuning it first")
-    p.add_argument("--waves-per-simd", type=int, default=2, choices=[2, 3, 4],
+    p.add_argument("--waves-per-simd", type=int, default=2, choices=[2, 3],
                    help="register budget of the integration kernel when not autotuning")
     p.add_argument("--wg-instances", type=int, default=0,
                    help="instances per workgroup when not autotuning (0 = as many as fit 512 lanes)")

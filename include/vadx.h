@@ -193,18 +193,17 @@ vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,
 vadx_status vadx_set_launch(vadx_ctx *ctx, int32_t mode, int32_t wg_instances, int32_t item_steps);
 
 /* Register budget of the persistent integration kernel in waves per SIMD: 2
- * (one 512-lane workgroup per CU, no spills; the default), 3 (room for two
- * 384-lane or three 256-lane workgroups per CU; a few spills outside the step
- * loop) or 4 (two 512-lane workgroups; a few spills per step). Takes effect
- * at the next vadx_plan; results do not depend on it. */
+ * (one 512-lane or two 256-lane workgroups per CU, no spills; the default) or
+ * 3 (three 256-lane workgroups per CU; a few spills outside the step loop).
+ * Takes effect at the next vadx_plan; results do not depend on it. */
 vadx_status vadx_set_waves_per_simd(vadx_ctx *ctx, int32_t waves);
 
 /* Autotuner of the launch shape for the current batch: times trial runs of
  * trial_steps steps (0 = 2000; no samples) of `run` in `ws` (device, at least
  * the size vadx_plan gave for `run`; its contents are overwritten) for
  * workgroup lane budgets of 64..512 lanes -- each region-count class then
- * packs floor(budget / n) instances per workgroup -- times 2, 3 or 4 waves
- * per SIMD, then queue items of 250, 1000 and 4000 steps, and keeps the fastest
+ * packs floor(budget / n) instances per workgroup -- times 2 or 3 waves per
+ * SIMD, then queue items of 250, 1000 and 4000 steps, and keeps the fastest
  * (persistent launch). With a cache_path (nullable) the choice is read from /
  * added to that JSON file, keyed by device, block length and the
  * region-count mix; a cached choice is applied without trials. *lanes,

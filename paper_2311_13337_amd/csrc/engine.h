@@ -11,7 +11,7 @@ namespace vadx {
 // Largest number of steps integrated between two workgroup barriers. A block
 // of B steps reads the delay rings before writing any of its own rates, which
 // is exact as long as B <= d_min + 1 (the shortest delay plus one).
-constexpr int kMaxBlock = 16;
+constexpr int kMaxBlock = 32;
 
 // One instance = one parameter combination on one connectome.
 struct InstDev {

@@ -273,10 +273,10 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 // memory), so the groups advance in step while every workgroup stays busy
 // until the queue is empty. The wait is bounded: on timeout the kernel
 // records an error and the workgroup stops.
-// OCC: waves per SIMD the register allocation must allow (2: one 512-lane
-// workgroup per CU, no spills; 3: two 384-lane or three 256-lane workgroups,
-// a few spills outside the step loop; 4: two 512-lane workgroups, a few
-// spills per step).
+// OCC: waves per SIMD the register allocation must allow (2: one 512-lane or
+// two 256-lane workgroups per CU, no spills; 3: three 256-lane workgroups, a
+// few spills outside the step loop). (A budget of 4 waves, 128 registers,
+// spills inside the step loop and measured slower than both.)
 template <int B, int VAR, int OCC>
 __global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
 {
@@ -377,6 +377,7 @@ static hipError_t launch_integrate_v(const IntegrateArgs &a, int n_groups, int b
     case 4: return launch_integrate_b<4, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     case 8: return launch_integrate_b<8, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     case 16: return launch_integrate_b<16, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 32: return launch_integrate_b<32, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -396,7 +397,6 @@ static hipError_t launch_integrate_o(const IntegrateArgs &a, int n_groups, int b
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
                             const QueueArgs *q, int grid, int occ, hipStream_t s)
 {
-    if (occ == 4) return launch_integrate_o<4>(a, n_groups, block_threads, q, grid, s);
     if (occ == 3) return launch_integrate_o<3>(a, n_groups, block_threads, q, grid, s);
     return launch_integrate_o<2>(a, n_groups, block_threads, q, grid, s);
 }
@@ -426,13 +426,13 @@ template <int OCC> static int resident(int block, int block_threads)
     case 4: return resident_b<4, OCC>(block_threads);
     case 8: return resident_b<8, OCC>(block_threads);
     case 16: return resident_b<16, OCC>(block_threads);
+    case 32: return resident_b<32, OCC>(block_threads);
     default: return 0;
     }
 }
 
 int persistent_blocks_per_cu(int block, int block_threads, int occ)
 {
-    if (occ == 4) return resident<4>(block, block_threads);
     if (occ == 3) return resident<3>(block, block_threads);
     return resident<2>(block, block_threads);
 }

@@ -24,6 +24,14 @@ using namespace vadx;
 
 namespace {
 
+// Groups sharing a block length: [first, first + n_groups) of the group table,
+// integrated by one launch of workgroups of `threads` lanes.
+struct BlockClass {
+    int block;
+    int32_t first, n_groups;
+    int threads;
+};
+
 struct HostConn {
     int32_t n = 0, nnz = 0;
     double len_min = 0.0, len_max = 0.0;   // over edges with w != 0
@@ -77,8 +85,9 @@ struct vadx_ctx {
     // plan
     bool planned = false;
     vadx_run plan_run{};
-    int block = 1;
-    int wg_threads = 64;
+    int block = 1;                       // longest block length of the plan
+    int wg_threads = 64;                 // widest workgroup of the plan
+    std::vector<BlockClass> classes;     // groups of one block length, launched together
     std::vector<InstDev> h_inst;
     std::vector<int32_t> h_perm;
     std::vector<GroupDev> h_groups;
@@ -402,23 +411,25 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     const int64_t ni = (int64_t)c->S.size();
     if (ni == 0) return fail(c, VADX_E_STATE, "no batch set");
     const int64_t ns = (r->n_steps - r->transient_steps) / r->tavg_steps;
-    // ring depths and the block length: a block of B steps reads histories up
-    // to B-1 steps ahead of its first step, so B <= d_min + 1; rings hold
-    // d_max + B + 1 slots so a block's writes never overwrite a value that a
-    // lane of the same block still has to read.
-    int64_t dmin_all = INT64_MAX;
+    // ring depths and block lengths: a block of B steps reads histories up to
+    // B-1 steps ahead of its first step, so B <= d_min + 1 (each instance's own
+    // shortest delay); rings hold d_max + B + 1 slots so a block's writes never
+    // overwrite a value that a lane of the same block still has to read.
     std::vector<int64_t> dmax(ni);
+    std::vector<int> blk(ni);
+    int bmax = 1;
     for (int64_t i = 0; i < ni; ++i) {
         const HostConn &hc = c->conns[c->conn_of[i]];
         const int64_t dm = hc.nnz ? host_delay(hc.len_min, c->v[i], r->dt_ms) : 1;
         dmax[i] = hc.nnz ? host_delay(hc.len_max, c->v[i], r->dt_ms) : 1;
-        dmin_all = std::min(dmin_all, dm);
         if (dmax[i] >= (1 << 20) - kMaxBlock - 2)
             return fail(c, VADX_E_UNSUPPORTED, "delay of %lld steps too long", (long long)dmax[i]);
+        int B = 1;
+        while (B * 2 <= kMaxBlock && B * 2 <= dm + 1) B *= 2;
+        blk[i] = B;
+        bmax = std::max(bmax, B);
     }
-    int B = 1;
-    while (B * 2 <= kMaxBlock && B * 2 <= dmin_all + 1) B *= 2;
-    c->block = B;
+    c->block = bmax;
     // delay tables: one per distinct (connectome, speed)
     std::map<std::pair<int32_t, uint32_t>, int32_t> tab;
     c->h_tables.clear();
@@ -441,29 +452,37 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         tab_of[i] = it->second;
     }
     c->packed_total = poff;
-    // groups: instances of one connectome, ordered by ring depth, up to
-    // `per` instances (and 512 lanes) per workgroup
+    // groups: instances of one block length and one connectome, ordered by ring
+    // depth, up to `per` instances (and the lane budget) per workgroup; one
+    // launch per block length (longest first)
     std::vector<int32_t> order(ni);
     for (int64_t i = 0; i < ni; ++i) order[i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (blk[a] != blk[b]) return blk[a] > blk[b];
         if (c->conn_of[a] != c->conn_of[b]) return c->conn_of[a] < c->conn_of[b];
         return dmax[a] < dmax[b];
     });
     c->h_groups.clear();
     c->h_perm = order;
-    int max_threads = 64;
+    c->classes.clear();
     for (int64_t s = 0; s < ni;) {
         const int32_t cid = c->conn_of[order[s]];
+        const int B = blk[order[s]];
         const int n = c->conns[cid].n;
         int per = std::max(1, c->wg_lanes / n);
         if (c->wg_instances_override > 0) per = std::min(per, c->wg_instances_override);
         int64_t e = s;
-        while (e < ni && e - s < per && c->conn_of[order[e]] == cid) ++e;
+        while (e < ni && e - s < per && c->conn_of[order[e]] == cid && blk[order[e]] == B) ++e;
+        if (c->classes.empty() || c->classes.back().block != B)
+            c->classes.push_back(BlockClass{B, (int32_t)c->h_groups.size(), 0, 64});
+        BlockClass &bc = c->classes.back();
         c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, 0});
-        max_threads = std::max(max_threads, (int)(((e - s) * n + 63) / 64 * 64));
+        bc.n_groups += 1;
+        bc.threads = std::max(bc.threads, (int)(((e - s) * n + 63) / 64 * 64));
         s = e;
     }
-    c->wg_threads = max_threads;
+    c->wg_threads = 64;
+    for (const BlockClass &bc : c->classes) c->wg_threads = std::max(c->wg_threads, bc.threads);
     // workspace layout (floats unless noted), each section 256-byte aligned
     c->h_inst.assign(ni, InstDev{});
     int64_t f_state = 0, f_acc = 0, f_ring = 0, f_samp = 0, f_fc = 0, f_trace = 0;
@@ -472,8 +491,8 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         InstDev &d = c->h_inst[i];
         d.S = c->S[i]; d.be = c->be[i]; d.ae = c->ae[i];
         d.n = hc.n;
-        d.D = (int32_t)(dmax[i] + B + 1);
-        d.Dp = d.D + B - 1;
+        d.D = (int32_t)(dmax[i] + blk[i] + 1);
+        d.Dp = d.D + blk[i] - 1;
         d.conn = c->conn_of[i];
         d.id = c->noise_key[(size_t)i];
         d.table_off = c->h_tables[tab_of[i]].off;
@@ -568,40 +587,48 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     a.I_init = c->model.I_init;
     a.seed = r->seed;
     a.integrator = r->integrator;
-    a.block = c->block;
     // default launch length: the whole run for the persistent queue (its only
-    // tail is then the end of the run), 10000 steps for one-workgroup-per-group
+    // tail is then the end of the run), 10000 steps for one-workgroup-per-group.
+    // Launch and item lengths are multiples of every block length (powers of 2
+    // up to the plan's longest).
     int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps
                                        : (c->launch_mode == 0 ? std::max<int64_t>(r->n_steps, 1) : 10000);
     chunk = std::max<int64_t>(chunk / c->block, 1) * c->block;
-    const int ng = (int)c->h_groups.size();
-    QueueArgs q{};
-    int grid = ng;
+    const int64_t item_steps = std::max<int64_t>(c->item_steps / c->block, 1) * c->block;
     if (c->launch_mode == 0) {
-        int *qb = (int *)((char *)ws + c->off_queue);
-        q.next = qb;
-        q.status = (uint32_t *)(qb + 1);
-        q.done = qb + 2;
-        q.n_groups = ng;
-        q.item_steps = std::max<int64_t>(c->item_steps / c->block, 1) * c->block;
-        q.max_spins = 1u << 26;
-        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads, c->occ);
-        if (per_cu <= 0) return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", c->wg_threads);
-        grid = std::min(ng, per_cu * c->cus);
-        HIP_TRY(c, launch_fill_u32(q.status, 1, 0u, st));
+        uint32_t *status = (uint32_t *)((char *)ws + c->off_queue) + 1;
+        HIP_TRY(c, launch_fill_u32(status, 1, 0u, st));
     }
     for (int64_t n0 = 0; n0 < r->n_steps; n0 += chunk) {
         a.n_begin = n0;
         a.n_end = std::min<int64_t>(r->n_steps, n0 + chunk);
-        hipEvent_t stop = nullptr;
-        if (timed) { vadx_status e = record(c, c->ev_int, &stop); if (e) return e; }
-        if (c->launch_mode == 0) {
-            q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
-            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, &q, grid, c->occ, st));
-        } else {
-            HIP_TRY(c, launch_integrate(a, ng, c->wg_threads, nullptr, ng, 2, st));
+        // one launch per block length, longest first, on the same stream
+        for (const BlockClass &bc : c->classes) {
+            a.block = bc.block;
+            a.groups = c->d_groups.p + bc.first;
+            const int ng = bc.n_groups;
+            hipEvent_t stop = nullptr;
+            if (timed) { vadx_status e = record(c, c->ev_int, &stop); if (e) return e; }
+            if (c->launch_mode == 0) {
+                int *qb = (int *)((char *)ws + c->off_queue);
+                QueueArgs q{};
+                q.next = qb;
+                q.status = (uint32_t *)(qb + 1);
+                q.done = qb + 2;
+                q.n_groups = ng;
+                q.item_steps = item_steps;
+                q.max_spins = 1u << 26;
+                const int per_cu = persistent_blocks_per_cu(bc.block, bc.threads, c->occ);
+                if (per_cu <= 0)
+                    return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", bc.threads);
+                const int grid = std::min(ng, per_cu * c->cus);
+                q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
+                HIP_TRY(c, launch_integrate(a, ng, bc.threads, &q, grid, c->occ, st));
+            } else {
+                HIP_TRY(c, launch_integrate(a, ng, bc.threads, nullptr, ng, 2, st));
+            }
+            if (timed) HIP_TRY(c, hipEventRecord(stop, st));
         }
-        if (timed) HIP_TRY(c, hipEventRecord(stop, st));
     }
     FcArgs f{};
     f.inst = c->d_inst.p;
@@ -668,7 +695,7 @@ vadx_status vadx_integrate(vadx_ctx *c, const vadx_run *r, void *ws, size_t ws_b
 vadx_status vadx_set_waves_per_simd(vadx_ctx *c, int32_t waves)
 {
     if (!c) return VADX_E_ARG;
-    if (waves != 0 && (waves < 2 || waves > 4)) return fail(c, VADX_E_ARG, "waves per SIMD must be 2, 3 or 4");
+    if (waves != 0 && waves != 2 && waves != 3) return fail(c, VADX_E_ARG, "waves per SIMD must be 2 or 3");
     c->occ = waves == 0 ? 2 : waves;
     c->planned = false;
     return VADX_OK;
@@ -679,10 +706,14 @@ vadx_status vadx_launch_info(vadx_ctx *c, int32_t *groups, int32_t *block_thread
 {
     if (!c) return VADX_E_ARG;
     if (!c->planned) return fail(c, VADX_E_STATE, "no plan");
-    int g = (int)c->h_groups.size();
-    if (c->launch_mode == 0) {
-        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads, c->occ);
-        g = std::min(g, per_cu * c->cus);
+    int g = 0;
+    for (const BlockClass &bc : c->classes) {
+        int gc = bc.n_groups;
+        if (c->launch_mode == 0) {
+            const int per_cu = persistent_blocks_per_cu(bc.block, bc.threads, c->occ);
+            gc = std::min(gc, per_cu * c->cus);
+        }
+        g = std::max(g, gc);
     }
     if (groups) *groups = (int32_t)c->h_groups.size();
     if (block_threads) *block_threads = c->wg_threads;
@@ -883,7 +914,7 @@ static bool tune_lookup(const char *path, const std::string &key, int *lanes, in
         if (std::sscanf(line.c_str() + pl + 8, "%d", &l) == 1 &&
             std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 &&
             std::sscanf(line.c_str() + pw + 17, "%d", &w) == 1 && l >= 64 && l <= 512 && it > 0 &&
-            w >= 2 && w <= 4) {
+            w >= 2 && w <= 3) {
             *lanes = l;
             *items = it;
             *occ = w;
@@ -1010,7 +1041,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
                 }
             }
             if (same) continue;
-            for (int w : {2, 3, 4}) {
+            for (int w : {2, 3}) {
                 if (result) break;
                 result = trial(l, 1000, w, &ms);
                 if (result == VADX_OK && (best_ms < 0 || ms < best_ms)) {
