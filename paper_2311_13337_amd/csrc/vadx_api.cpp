@@ -593,7 +593,9 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     // up to the plan's longest).
     int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps
                                        : (c->launch_mode == 0 ? std::max<int64_t>(r->n_steps, 1) : 10000);
-    chunk = std::max<int64_t>(chunk / c->block, 1) * c->block;
+    // (a launch that reaches the end of the run may end on a partial block)
+    chunk = chunk >= r->n_steps ? std::max<int64_t>(r->n_steps, 1)
+                                : std::max<int64_t>(chunk / c->block, 1) * c->block;
     const int64_t item_steps = std::max<int64_t>(c->item_steps / c->block, 1) * c->block;
     if (c->launch_mode == 0) {
         uint32_t *status = (uint32_t *)((char *)ws + c->off_queue) + 1;
