@@ -224,14 +224,19 @@ template <class T> struct TFShared {
     T xe, xi, r, r2, r3;
     T de, he1, he2;             // d_e = 1/(C_m/G + tau_e) and its first two derivatives in G
     T cexe, cixi;               // c_e xe, c_i xi
+    // tau_e == tau_i only: phi = d_e / G^4 with its derivatives in G, and the
+    // jets of 1/tau_V = d_e and tau_V = C_m/G + tau_e
+    T phi, phi1, phi2;
+    Jet<T> ITV, TV;
 };
 
-template <class T> VADX_HD TFShared<T> tf_shared(const KModel &M, T xe, T xi)
+template <bool EQ, class T> VADX_HD TFShared<T> tf_shared(const KModel &M, T xe, T xi)
 {
     TFShared<T> g;
+    const T aE = T(M.aE), aI = T(M.aI);
     g.xe = xe;
     g.xi = xi;
-    T G = fmaf_(T(M.aE), xe, fmaf_(T(M.aI), xi, T(M.gL)));
+    T G = fmaf_(aE, xe, fmaf_(aI, xi, T(M.gL)));
     g.r = rcp(G);
     g.r2 = g.r * g.r;
     g.r3 = g.r2 * g.r;
@@ -242,6 +247,16 @@ template <class T> VADX_HD TFShared<T> tf_shared(const KModel &M, T xe, T xi)
     g.he2 = T(-2) * T(M.tau_e) * g.he1 * qe;
     g.cexe = T(M.ce) * xe;
     g.cixi = T(M.ci) * xi;
+    if constexpr (EQ) {
+        // (ln phi)' = -(3 + tau d_e)/G, phi'' = phi (12 + 6 tau d_e + 2 (tau d_e)^2) / G^2
+        T td = T(M.tau_e) * g.de;
+        g.phi = g.r2 * g.r2 * g.de;
+        g.phi1 = -g.phi * g.r * (T(3) + td);
+        g.phi2 = g.phi * g.r2 * fmaf_(td, fmaf_(T(2), td, T(6)), T(12));
+        g.ITV = jofG(g.de, g.he1, g.he2, aE, aI);
+        // tau_V = T_eff + tau_e = C_m/G + tau_e
+        g.TV = jofG(fmaf_(T(M.Cm), g.r, T(M.tau_e)), -T(M.Cm) * g.r2, T(2) * T(M.Cm) * g.r3, aE, aI);
+    }
     return g;
 }
 
@@ -281,16 +296,10 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, const TFShared<T> &g, T W, T &
     PI.bb = T(M.ce2bE2) * xe;
     Jet<T> S2, ITV, TV;                              // 2 sigma_V^2, 1/tau_V, tau_V
     if constexpr (EQ) {
-        // S2 = Pi phi(G), phi = d_e / G^4: (ln phi)' = -(3 + tau d_e)/G,
-        // phi'' = phi (12 + 6 tau d_e + 2 (tau d_e)^2) / G^2
-        T td = T(M.tau_e) * de;
-        T phi = r2 * r2 * de;
-        T phi1 = -phi * r * (T(3) + td);
-        T phi2 = phi * r2 * fmaf_(td, fmaf_(T(2), td, T(6)), T(12));
-        S2 = jmulG(PI, phi, phi1, phi2, aE, aI, T(M.aEE), T(M.aEI), T(M.aII));
-        ITV = jofG(de, he1, he2, aE, aI);
-        // tau_V = T_eff + tau_e = C_m/G + tau_e
-        TV = jofG(fmaf_(T(M.Cm), r, T(M.tau_e)), -T(M.Cm) * r2, T(2) * T(M.Cm) * r3, aE, aI);
+        // S2 = Pi phi(G), phi = d_e / G^4
+        S2 = jmulG(PI, g.phi, g.phi1, g.phi2, aE, aI, T(M.aEE), T(M.aEI), T(M.aII));
+        ITV = g.ITV;
+        TV = g.TV;
     } else {
         // A_e = c_e xe A^2 / G^4 and A_i = c_i xi B^2 / G^4 weighted separately
         Jet<T> Ae, Ai;
@@ -381,8 +390,8 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
     T xe1 = maxf_(exc + T(M.cF[1][0]), T(M.x_floor));
     T xi1 = maxf_(I + T(M.cF[1][1]), T(M.x_floor));
     T muVe, muVi;
-    const TFShared<T> g0 = tf_shared(M, xe0, xi0);
     constexpr bool EQ = (VAR & kVarEq) != 0;
+    const TFShared<T> g0 = tf_shared<EQ>(M, xe0, xi0);
     Jet<T> Fe = transfer<EQ>(M, 0, g0, X[5], muVe);
     Jet<T> Fi;
     if constexpr ((VAR & kVarSame) != 0) {
@@ -390,7 +399,7 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
         (void)xi1;
         Fi = transfer<EQ>(M, 1, g0, X[6], muVi);
     } else {
-        const TFShared<T> g1 = tf_shared(M, xe1, xi1);
+        const TFShared<T> g1 = tf_shared<EQ>(M, xe1, xi1);
         Fi = transfer<EQ>(M, 1, g1, X[6], muVi);
     }
     const T iT = T(M.invT);

@@ -13,9 +13,11 @@ void mh_tf(const vadx_model *m, int pop, float xe, float xi, float W, float *out
 {
     KModel k = make_kmodel(*m);
     float mu = 0.f;
-    const TFShared<float> g = tf_shared(k, xe, xi);
-    Jet<float> F = m->tau_e == m->tau_i ? transfer<true>(k, pop, g, W, mu)
-                                        : transfer<false>(k, pop, g, W, mu);
+    Jet<float> F;
+    if (m->tau_e == m->tau_i)
+        F = transfer<true>(k, pop, tf_shared<true>(k, xe, xi), W, mu);
+    else
+        F = transfer<false>(k, pop, tf_shared<false>(k, xe, xi), W, mu);
     out[0] = F.v; out[1] = F.a; out[2] = F.b; out[3] = F.aa; out[4] = F.ab; out[5] = F.bb; out[6] = mu;
 }
 
