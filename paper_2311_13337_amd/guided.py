@@ -58,7 +58,7 @@ class GuidedConfig:
     n_check: int = 4096                # grid points simulated plainly to measure the error
     chunk: int = 16384                 # instances per simulation launch
     err_bound: float = 0.05
-    target_exceed: float = 0.045       # audit estimate of the grid fraction above err_bound
+    target_exceed: float = 0.04        # audit estimate of the grid fraction above err_bound
     adaptive: bool = True
 
 
