@@ -179,3 +179,44 @@ class RunConfig:
 RUN_SMALL = RunConfig(n_steps=10000, transient_steps=0)           # 1 s, no transient
 RUN_UNIFORM = RunConfig(n_steps=100000, transient_steps=10000)    # 10 s, 1 s transient
 RUN_UNEVEN = RunConfig(n_steps=50000, transient_steps=10000)      # 5 s, 1 s transient
+
+
+def synthetic_rate_series(n_inst: int, n: int, n_samples: int, seed: int = 5,
+                          period_ms: float = 1.0) -> np.ndarray:
+    """Seeded stand-in for stored excitatory rate samples, [n_inst][n_samples][n]
+    float32 in kHz, with the mix of behaviours the analysis metrics separate:
+    Up/Down alternation (Down ~0.5 Hz, Up 8-30 Hz, exponential state lengths of
+    tens to hundreds of ms), oscillations shared between regions with
+    region-specific phase lags plus coloured noise, random-walk (1/f^2) noise,
+    flat regions and regions whose range stays below 1 Hz."""
+    rng = np.random.default_rng(seed)
+    t_ms = np.arange(n_samples) * period_ms
+    out = np.empty((n_inst, n_samples, n), np.float32)
+    for i in range(n_inst):
+        f0 = rng.uniform(2.0, 60.0)                       # shared rhythm of this instance (Hz)
+        kind = rng.choice(5, size=n, p=[0.3, 0.35, 0.2, 0.05, 0.1])
+        for k in range(n):
+            if kind[k] == 0:                              # Up/Down
+                x = np.empty(n_samples)
+                pos, up = 0, bool(rng.integers(2))
+                lo, hi = rng.uniform(2e-4, 8e-4), rng.uniform(8e-3, 3e-2)
+                while pos < n_samples:
+                    d = max(1, int(rng.exponential(rng.uniform(40, 400) / period_ms)))
+                    x[pos:pos + d] = hi if up else lo
+                    pos += d
+                    up = not up
+                x = x + rng.standard_normal(n_samples) * 3e-4 * rng.random()
+            elif kind[k] == 1:                            # shared oscillation with a lag
+                lag = rng.uniform(-np.pi, np.pi)
+                amp = rng.uniform(5e-4, 5e-3)
+                noise = np.cumsum(rng.standard_normal(n_samples)) * 2e-5
+                x = 4e-3 + amp * np.cos(2 * np.pi * f0 * t_ms / 1000.0 + lag) + noise \
+                    + rng.standard_normal(n_samples) * amp * 0.2
+            elif kind[k] == 2:                            # random walk around a mean
+                x = 5e-3 + np.cumsum(rng.standard_normal(n_samples)) * rng.uniform(1e-5, 1e-4)
+            elif kind[k] == 3:                            # flat
+                x = np.full(n_samples, rng.uniform(1e-3, 1e-2))
+            else:                                         # small fluctuations (< 1 Hz range)
+                x = 3.85e-3 + rng.standard_normal(n_samples) * 5e-5
+            out[i, :, k] = np.maximum(x, 0.0)
+    return out
