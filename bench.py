@@ -61,7 +61,7 @@ def workload(name):
     if name == "uneven":
         conns = [conn, inputs.synthetic_connectome(84), inputs.synthetic_connectome(200)]
         return conns, inputs.grid_uneven(8192, seed=3), inputs.RUN_UNEVEN, (
-            "uneven batch in one persistent launch: 8192 instances, a third each on 68-, 84- and "
+            "uneven batch, one persistent launch per block length: 8192 instances, a third each on 68-, 84- and "
             "200-region synthetic connectomes, S, b_e, a_e uniform in the sweep box, v uniform in "
             "1-10 m/s (ring depths 21-2001 steps); 50000 Heun steps of 0.1 ms (5 s), FC after a "
             "1 s transient")
