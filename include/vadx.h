@@ -296,6 +296,80 @@ vadx_status vadx_mlp_select(vadx_mlp *mlp, const float *score, int64_t n, int64_
                             float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
                             int64_t capacity, int64_t *n_sel);
 
+/* ---------------------------------------------------------------------------
+ * Analysis metrics of Section 2.6 (Table 2) over stored excitatory rate
+ * samples, one result per instance (mean_FC is vadx_stats.fc_mean):
+ *  - window: the last `window` samples (a power of two, at most 16384; 0 = the
+ *    largest power of two not above the sample count); every metric uses it.
+ *  - psd: Welch's average of modified periodograms per region (segments of
+ *    `segment` samples, a power of two in [16, min(window, 8192)], 0 =
+ *    min(1024, window); hop segment/2; each segment's mean removed; periodic
+ *    Hann window), one-sided density in Hz^2/Hz of the rate in Hz; the
+ *    instance spectrum is the mean over regions. psd_peak_bin / psd_fmax_hz /
+ *    psd_ampmax: its largest value among bins 1..segment/2 (lowest bin on
+ *    ties). psd_slope_a, psd_log10_b: least-squares fit of
+ *    log10 P = log10 b - a log10 f over the bins with fit_lo_hz <= f <=
+ *    fit_hi_hz and P > 0 (psd_fit_bins of them; a = log10 b = 0 when fewer
+ *    than 2) -- the paper's fit of log(PSD) to log(b / f^a).
+ *  - mean_pli: mean over region pairs k < l of the phase lag index
+ *    |mean_t sign(Im(z_k(t) conj z_l(t)))| (Stam et al. 2007), z the discrete
+ *    analytic signal of the region's window with its mean removed (DFT, bin 0
+ *    zeroed, bins 1..window/2-1 doubled, negative bins zeroed, inverse DFT);
+ *    0 for one region.
+ *  - Up/Down states per region on the stored single-precision rates (kHz):
+ *    r = max - min over the window, centre = min + r/2, half-band
+ *    h = ud_band r (single precision); a sample above centre + h enters Up,
+ *    below centre - h enters Down; regions with r < ud_min_range_khz have no
+ *    states; a state lasts from the sample that entered it to the one that
+ *    left it, and the states cut by the window's ends are not counted.
+ *    ud_up_ms / ud_down_ms: mean durations over every counted state of every
+ *    region (0 without states); ud_*_count and ud_*_samples: their number and
+ *    summed length in samples. */
+typedef struct vadx_analysis_cfg {
+    int32_t window, segment;
+    double fit_lo_hz, fit_hi_hz;
+    float ud_band, ud_min_range_khz;
+} vadx_analysis_cfg;
+
+typedef struct vadx_analysis {
+    float psd_fmax_hz, psd_ampmax, psd_slope_a, psd_log10_b;
+    float mean_pli, ud_up_ms, ud_down_ms, reserved;
+    int32_t psd_peak_bin, psd_fit_bins, ud_up_count, ud_down_count;
+    int64_t ud_up_samples, ud_down_samples;
+} vadx_analysis;
+
+/* Defaults: window 0, segment 0, fit band 1-100 Hz, ud_band 0.1,
+ * ud_min_range_khz 1e-3 (1 Hz). */
+vadx_status vadx_analysis_defaults(vadx_analysis_cfg *out);
+
+/* Bytes of device workspace the analysis needs to take regions_per_pass
+ * regions per pass (instances are processed in passes of whole instances;
+ * more workspace, fewer passes), for series of n_samples samples and
+ * instances of at most n_max regions. About 12 * window bytes per region
+ * (the window and its analytic signal). */
+vadx_status vadx_analysis_ws_bytes(int64_t n_samples, int32_t n_max, int64_t regions_per_pass,
+                                   const vadx_analysis_cfg *cfg, size_t *bytes);
+
+/* Analysis of n_inst series given as device arrays samples [n_inst][n_samples][n]
+ * (FP32, kHz; the layout vadx_read_samples returns), sampled every
+ * sample_period_ms. ws: device workspace (256-byte aligned, caller-owned,
+ * contents overwritten) of at least the size vadx_analysis_ws_bytes gives for
+ * one instance (VADX_E_OOM otherwise). out: device array of n_inst results.
+ * psd_out (device, nullable): [n_inst][n][segment/2 + 1] region spectra;
+ * pli_out (device, nullable): [n_inst][n][n] PLI matrices (diagonal 0). 1 <= n
+ * <= 512. Stream-ordered on ctx's stream; no host synchronisation. */
+vadx_status vadx_analyze_series(vadx_ctx *ctx, const float *samples, int64_t n_inst, int32_t n,
+                                int64_t n_samples, double sample_period_ms,
+                                const vadx_analysis_cfg *cfg, void *ws, size_t ws_bytes,
+                                vadx_analysis *out, float *psd_out, float *pli_out);
+
+/* The same analysis over the samples of the last vadx_integrate (any mix of
+ * region counts; sample period tavg_steps * dt_ms) held in its workspace,
+ * which must still be alive. out: device array, one result per instance of
+ * the batch. */
+vadx_status vadx_analyze(vadx_ctx *ctx, const vadx_analysis_cfg *cfg, void *ws, size_t ws_bytes,
+                         vadx_analysis *out);
+
 /* Arithmetic of one region-step in this library's formulation, counted by
  * running the kernel's own model code with an operation-counting scalar:
  * single- and double-precision FLOPs (add, mul = 1, fma = 2, transcendental =

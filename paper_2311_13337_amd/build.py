@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvadx.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "vadx_api.cpp", "mlp.hip", "mlp_api.cpp", "select.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "vadx_api.cpp", "mlp.hip", "mlp_api.cpp", "select.hip",
+                                              "analysis.hip", "analysis_api.cpp")]
 HOST_SOURCES = [os.path.join(CSRC, "opcount.cpp")]   # plain C++ (g++), no device code
 ARCH = os.environ.get("VADX_OFFLOAD_ARCH", "gfx950")
 

@@ -16,6 +16,7 @@
 #include <utility>
 #include <vector>
 
+#include "analysis_engine.h"
 #include "engine.h"
 #include "kmodel.h"
 #include "vadx.h"
@@ -1066,5 +1067,46 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     if (waves_out) *waves_out = best_w;
     if (lanes_out) *lanes_out = best_l;
     if (item_steps_out) *item_steps_out = best_i;
+    return VADX_OK;
+}
+
+// ---------------------------------------------------------------- analysis
+extern "C" vadx_status vadx_analyze_series(vadx_ctx *c, const float *samples, int64_t n_inst,
+                                           int32_t n, int64_t n_samples, double sample_period_ms,
+                                           const vadx_analysis_cfg *cfg, void *ws, size_t ws_bytes,
+                                           vadx_analysis *out, float *psd_out, float *pli_out)
+{
+    if (!c) return VADX_E_ARG;
+    if (n_inst < 0) return fail(c, VADX_E_ARG, "negative instance count");
+    if (n < 1 || n > 512) return fail(c, VADX_E_ARG, "region count must be in [1, 512]");
+    std::vector<int64_t> off((size_t)n_inst);
+    std::vector<int32_t> ns((size_t)n_inst, n);
+    for (int64_t i = 0; i < n_inst; ++i) off[(size_t)i] = i * n_samples * n;
+    AnInstances in{samples, off.data(), ns.data(), n_inst, n_samples};
+    std::string err;
+    vadx_status st = run_analysis(c->device, c->stream, in, sample_period_ms, cfg, ws, ws_bytes, out,
+                                  psd_out, pli_out, err);
+    if (st) return fail(c, st, "%s", err.c_str());
+    return VADX_OK;
+}
+
+extern "C" vadx_status vadx_analyze(vadx_ctx *c, const vadx_analysis_cfg *cfg, void *ws,
+                                    size_t ws_bytes, vadx_analysis *out)
+{
+    if (!c) return VADX_E_ARG;
+    if (!c->ran) return fail(c, VADX_E_STATE, "no samples: call vadx_integrate first");
+    const size_t ni = c->h_inst.size();
+    std::vector<int64_t> off(ni);
+    std::vector<int32_t> ns(ni);
+    for (size_t i = 0; i < ni; ++i) {
+        off[i] = c->h_inst[i].samp_off;
+        ns[i] = c->h_inst[i].n;
+    }
+    AnInstances in{(const float *)c->ws, off.data(), ns.data(), (int64_t)ni, c->n_samples};
+    const double period = (double)c->plan_run.tavg_steps * c->plan_run.dt_ms;
+    std::string err;
+    vadx_status st = run_analysis(c->device, c->stream, in, period, cfg, ws, ws_bytes, out, nullptr,
+                                  nullptr, err);
+    if (st) return fail(c, st, "%s", err.c_str());
     return VADX_OK;
 }

@@ -31,7 +31,10 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_set_waves_per_simd", "vadx_launch_info", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
-           "vadx_mlp_predict", "vadx_mlp_select")
+           "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
+           "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze")
+ANALYSIS_NAMES = ("psd_fmax_hz", "psd_ampmax", "psd_slope_a", "psd_log10_b", "mean_pli",
+                  "ud_up_ms", "ud_down_ms")
 MLP_PARAMS = 17926
 
 
@@ -61,6 +64,18 @@ class vadx_mlp_cfg(C.Structure):
     _fields_ = [("x_lo", C.c_float * 4), ("x_hi", C.c_float * 4), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("hip_stream", C.c_void_p)]
+
+
+class vadx_analysis_cfg(C.Structure):
+    _fields_ = [("window", C.c_int32), ("segment", C.c_int32), ("fit_lo_hz", C.c_double),
+                ("fit_hi_hz", C.c_double), ("ud_band", C.c_float), ("ud_min_range_khz", C.c_float)]
+
+
+class vadx_analysis(C.Structure):
+    _fields_ = [(f, C.c_float) for f in ANALYSIS_NAMES] + [
+        ("reserved", C.c_float), ("psd_peak_bin", C.c_int32), ("psd_fit_bins", C.c_int32),
+        ("ud_up_count", C.c_int32), ("ud_down_count", C.c_int32),
+        ("ud_up_samples", C.c_int64), ("ud_down_samples", C.c_int64)]
 
 
 class vadx_stats(C.Structure):
@@ -128,6 +143,12 @@ def lib():
             "vadx_mlp_predict": (st, [vp, vp, C.c_int64, vp, vp, vp, C.c_int32, C.c_int32]),
             "vadx_mlp_select": (st, [vp, vp, C.c_int64, C.c_int64, C.c_float, C.c_uint32, vp, vp,
                                      C.c_int64, P(C.c_int64)]),
+            "vadx_analysis_defaults": (st, [P(vadx_analysis_cfg)]),
+            "vadx_analysis_ws_bytes": (st, [C.c_int64, C.c_int32, C.c_int64, P(vadx_analysis_cfg),
+                                            P(C.c_size_t)]),
+            "vadx_analyze_series": (st, [vp, vp, C.c_int64, C.c_int32, C.c_int64, C.c_double,
+                                         P(vadx_analysis_cfg), vp, C.c_size_t, vp, vp, vp]),
+            "vadx_analyze": (st, [vp, P(vadx_analysis_cfg), vp, C.c_size_t, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -287,6 +308,53 @@ class Context:
         a, b, c, d = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
         self._check(lib().vadx_kernel_time(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         return a.value, b.value, c.value, d.value
+
+    def vadx_analyze_series(self, samples, n_samples: int, n: int, period_ms: float,
+                            cfg: "vadx_analysis_cfg", ws, out, psd_out=None, pli_out=None):
+        """samples: device tensor [n_inst][n_samples][n] float32; ws: device tensor
+        (uint8, 256-byte aligned); out: device tensor of n_inst * 64 bytes."""
+        n_inst = samples.shape[0]
+        self._check(lib().vadx_analyze_series(
+            self.h, C.c_void_p(samples.data_ptr()), n_inst, n, n_samples, period_ms, C.byref(cfg),
+            C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(out.data_ptr()),
+            None if psd_out is None else C.c_void_p(psd_out.data_ptr()),
+            None if pli_out is None else C.c_void_p(pli_out.data_ptr())))
+
+    def vadx_analyze(self, cfg: "vadx_analysis_cfg", ws, out):
+        self._check(lib().vadx_analyze(self.h, C.byref(cfg), C.c_void_p(ws.data_ptr()),
+                                       ws.numel() * ws.element_size(), C.c_void_p(out.data_ptr())))
+
+
+def vadx_analysis_defaults() -> vadx_analysis_cfg:
+    c = vadx_analysis_cfg()
+    s = lib().vadx_analysis_defaults(C.byref(c))
+    if s != VADX_OK:
+        raise VadxError(s, "analysis defaults")
+    return c
+
+
+def vadx_analysis_ws_bytes(n_samples: int, n_max: int, regions_per_pass: int,
+                           cfg: vadx_analysis_cfg | None = None) -> int:
+    cfg = cfg or vadx_analysis_defaults()
+    b = C.c_size_t()
+    s = lib().vadx_analysis_ws_bytes(n_samples, n_max, regions_per_pass, C.byref(cfg), C.byref(b))
+    if s != VADX_OK:
+        raise VadxError(s, "invalid analysis sizes or settings")
+    return b.value
+
+
+def analysis_to_numpy(out) -> np.ndarray:
+    """Device tensor of vadx_analysis records -> numpy structured array."""
+    raw = out.cpu().numpy().tobytes()
+    n = len(raw) // C.sizeof(vadx_analysis)
+    arr = (vadx_analysis * n).from_buffer_copy(raw)
+    return np.ctypeslib.as_array(arr).copy()
+
+
+def analysis_out(n_inst: int, device: int = 0):
+    """Device buffer for n_inst vadx_analysis records."""
+    import torch
+    return torch.zeros(n_inst * C.sizeof(vadx_analysis), dtype=torch.uint8, device=f"cuda:{device}")
 
 
 def make_run(cfg, integrator: int = VADX_HEUN, noise_off: bool = False, chunk_steps: int = 0,

@@ -51,3 +51,25 @@ def test_create_without_device_fails_cleanly():
     s = vadx.lib().vadx_create(0, None, C.byref(h))
     assert s in (vadx.VADX_E_HIP, vadx.VADX_E_ARG)
     assert vadx.lib().vadx_last_error(None).startswith(b"hipGetDeviceCount")
+
+
+def test_analysis_workspace_query_and_defaults():
+    """Host-only parts of the analysis ABI: defaults and the workspace size
+    (12 bytes per window sample and region dominate) with its argument checks."""
+    cfg = vadx.vadx_analysis_defaults()
+    assert (cfg.window, cfg.segment, cfg.fit_lo_hz, cfg.fit_hi_hz) == (0, 0, 1.0, 100.0)
+    b1 = vadx.vadx_analysis_ws_bytes(9000, 68, 68)
+    b2 = vadx.vadx_analysis_ws_bytes(9000, 68, 2 * 68)
+    per = (b2 - b1) / 68
+    assert 12 * 8192 < per < 12 * 8192 + 4096
+    cfg.window = 4096
+    assert vadx.vadx_analysis_ws_bytes(9000, 68, 136, cfg) < b2
+    for args in [(9000, 0, 68), (9000, 513, 1024), (9000, 68, 67), (15, 4, 4)]:
+        with pytest.raises(vadx.VadxError):
+            vadx.vadx_analysis_ws_bytes(*args)
+    for field, value in [("window", 3000), ("window", 32768), ("segment", 4), ("segment", 16384),
+                         ("fit_hi_hz", float("nan")), ("ud_min_range_khz", -1.0)]:
+        bad = vadx.vadx_analysis_defaults()
+        setattr(bad, field, value)
+        with pytest.raises(vadx.VadxError):
+            vadx.vadx_analysis_ws_bytes(40000, 68, 68, bad)

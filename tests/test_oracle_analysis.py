@@ -13,6 +13,7 @@ def test_window_length():
     assert A.analysis_window(300) == 256
     assert A.analysis_window(1) == 1
     assert A.analysis_window(9000, 4096) == 4096
+    assert A.analysis_window(50000) == 16384
     with pytest.raises(ValueError):
         A.analysis_window(9000, 3000)
     with pytest.raises(ValueError):
