@@ -12,8 +12,8 @@ The paper names these metrics and gives the fitted law, log PSD = log(b / f^a);
 the remaining definitions are readings:
 
 * Analysis window: the last N_a samples of the post-transient series, N_a the
-  largest power of two not above their number (or a caller's power of two).
-  Every metric uses the same window.
+  largest power of two not above their number and 16384 (16.4 s at 1-ms
+  samples), or a caller's power of two. Every metric uses the same window.
 * PSD: Welch's average of modified periodograms per region -- segments of L
   samples (a power of two, default 1024) advancing by L/2, each with its own
   mean removed and multiplied by the periodic Hann window
@@ -46,6 +46,7 @@ from __future__ import annotations
 import numpy as np
 
 DEFAULT_SEGMENT = 1024
+MAX_WINDOW = 16384
 DEFAULT_FIT_BAND_HZ = (1.0, 100.0)
 DEFAULT_UD_BAND = 0.1
 DEFAULT_UD_MIN_RANGE_KHZ = 1e-3
@@ -59,7 +60,7 @@ def analysis_window(n_samples: int, window: int = 0) -> int:
         return window
     if n_samples < 1:
         raise ValueError("no samples")
-    return 1 << (int(n_samples).bit_length() - 1)
+    return min(1 << (int(n_samples).bit_length() - 1), MAX_WINDOW)
 
 
 def hann_periodic(L: int) -> np.ndarray:
