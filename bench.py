@@ -45,6 +45,10 @@ def parse():
     p.add_argument("--cpu-sample-steps", type=int, default=10000)
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_uniform.json"),
                    help="HBM bytes per launch measured with rocprofv3 counters, if present")
+    p.add_argument("--no-analysis", action="store_true",
+                   help="skip the analysis-metric pass over the sweep's samples")
+    p.add_argument("--analysis-reps", type=int, default=3)
+    p.add_argument("--analysis-cpu-instances", type=int, default=8)
     p.add_argument("--no-guided", action="store_true",
                    help="skip the surrogate-guided sweep of the 32^4 grid (about a minute and a half)")
     p.add_argument("--run-steps", type=int, default=0,
@@ -202,6 +206,8 @@ def main():
                       "steps_per_run": cfg.n_steps, "dt_ms": cfg.dt_ms,
                       "parallelism": "single GPU", "launch_shape": shape},
            "roofline": roof}
+    if not args.no_analysis and args.run_steps == 0:
+        out["analysis"] = analysis_line(sw, conns, batch, cfg, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(conns, batch, cfg, args.cpu_sample_instances,
                                            args.cpu_sample_steps)
@@ -210,6 +216,94 @@ def main():
         torch.cuda.empty_cache()
         out["guided_vs_plain"] = guided_line()
     print(json.dumps(out), flush=True)
+
+
+def analysis_line(sw, conns, batch, cfg, args):
+    """The analysis metrics of Table 2 over the samples of the timed sweep
+    (vadx_analyze on the integration workspace): time per pass over the whole
+    batch, per-kernel times, the roofline of the dominant kernel, and the FP64
+    oracle's time per instance on synthetic series of the same shape."""
+    import numpy as np
+    import torch
+
+    from paper_2311_13337_amd import vadx
+    ctx = sw.ctx
+    n_inst = len(batch)
+    n_max = max(c.n for c in conns)
+    regions = np.array([c.n for c in conns], np.int64)[batch.conn]
+    R = int(regions.sum())
+    acfg = vadx.vadx_analysis_defaults()
+    ns = cfg.n_samples
+    Na = min(1 << (ns.bit_length() - 1), 16384)
+    L = min(1024, Na)
+    nb2 = L // 2 + 1
+    n_seg = (Na - L) // (L // 2) + 1
+    ws = torch.empty(vadx.vadx_analysis_ws_bytes(ns, n_max, R, acfg), dtype=torch.uint8,
+                     device="cuda:0")
+    out = vadx.analysis_out(n_inst)
+    ctx.vadx_analyze(acfg, ws, out)              # warm-up
+    torch.cuda.synchronize()
+    ctx.vadx_enable_timing(True)
+    vadx.analysis_kernel_time(ctx)               # reset
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = args.analysis_reps
+    e0.record()
+    for _ in range(reps):
+        ctx.vadx_analyze(acfg, ws, out)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = vadx.analysis_kernel_time(ctx)
+    ctx.vadx_enable_timing(False)
+    ms = e0.elapsed_time(e1) / reps
+    res = vadx.analysis_to_numpy(out)
+    # algorithmic bytes (HBM) and FLOPs per pass, per kernel
+    pairs = float(((regions * (regions - 1)) // 2).sum())
+    work = {
+        "an_transpose_kernel": {"bytes": 8.0 * Na * R},
+        "an_welch_kernel": {"bytes": 4.0 * Na * R + 4.0 * nb2 * R,
+                            "flop": R * n_seg * 5.0 * L * np.log2(L)},
+        "an_hilbert_kernel": {"bytes": 12.0 * Na * R, "flop": R * 2 * 5.0 * Na * np.log2(Na)},
+        "an_pli_kernel": {"bytes": 8.0 * Na * R, "flop": 3.0 * pairs * Na},
+        "an_ud_kernel": {"bytes": 4.0 * Na * R},
+        "an_final_kernel": {"bytes": 4.0 * nb2 * R},
+    }
+    kernels = {}
+    for k, (nl, kms) in kt.items():
+        d = {"ms": round(kms / reps, 3), "launches": nl // reps}
+        if kms > 0:
+            d["GB_s"] = round(work[k]["bytes"] / (kms / reps / 1000.0) / 1e9, 1)
+            if "flop" in work[k]:
+                d["TFLOP_s"] = round(work[k]["flop"] / (kms / reps / 1000.0) / 1e12, 2)
+        kernels[k] = d
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    dms = kernels[dom]["ms"] / 1000.0
+    if dom == "an_pli_kernel":
+        # sign accumulation of Im(z_k conj z_l): plain VALU arithmetic
+        ach = work[dom]["flop"] / dms / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": MI355X_FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / MI355X_FP32_VECTOR_TFLOPS, 4)}
+    else:
+        ach = work[dom]["bytes"] / dms / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": MI355X_HBM_GBPS, "unit": "GB/s",
+                "frac": round(ach / MI355X_HBM_GBPS, 4)}
+    roof["kernel"] = dom
+    # the oracle on synthetic series of the same shape (bounded sample)
+    from oracle import analysis as oa
+
+    from paper_2311_13337_amd import inputs
+    S = inputs.synthetic_rate_series(args.analysis_cpu_instances, int(regions.min()), ns, seed=9)
+    t0 = time.perf_counter()
+    for i in range(S.shape[0]):
+        oa.analyze_instance(S[i], cfg.tavg_steps * cfg.dt_ms)
+    cpu_s = (time.perf_counter() - t0) / S.shape[0]
+    return {"metric": "analysed instances per s", "value": round(n_inst / (ms / 1000.0), 1),
+            "ms_per_pass": round(ms, 3), "instances": n_inst, "regions": R, "window": Na,
+            "segment": L, "kernels": kernels, "roofline": roof,
+            "finite": bool(np.isfinite(res["psd_slope_a"]).all() and np.isfinite(res["mean_pli"]).all()),
+            "mean_pli_mean": round(float(res["mean_pli"].mean()), 4),
+            "cpu_oracle": {"s_per_instance": round(cpu_s, 4), "cores": 1, "kind": "oracle",
+                           "sample": f"{S.shape[0]} synthetic instances of {int(regions.min())} "
+                                     f"regions x {ns} samples (numpy FP64, one process)"}}
 
 
 def guided_line():

@@ -370,6 +370,13 @@ vadx_status vadx_analyze_series(vadx_ctx *ctx, const float *samples, int64_t n_i
 vadx_status vadx_analyze(vadx_ctx *ctx, const vadx_analysis_cfg *cfg, void *ws, size_t ws_bytes,
                          vadx_analysis *out);
 
+/* Analysis kernel timing: with vadx_enable_timing on, HIP events bracket each
+ * analysis launch; launches[6] and ms[6] (host) receive, per kernel -- window
+ * transpose, Welch spectra, analytic signals, phase lag index, Up/Down
+ * durations, per-instance reduction -- the launch count and summed duration
+ * since the last call (which resets them). Waits for the recorded events. */
+vadx_status vadx_analysis_kernel_time(vadx_ctx *ctx, int64_t *launches, double *ms);
+
 /* Arithmetic of one region-step in this library's formulation, counted by
  * running the kernel's own model code with an operation-counting scalar:
  * single- and double-precision FLOPs (add, mul = 1, fma = 2, transcendental =

@@ -23,6 +23,29 @@ __device__ inline float2 cmulconj(float2 a, float2 b)   // a * conj(b)
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
+// Twiddle factors exp(-2 pi i j / kTwMax) from two LDS tables of kTwSplit
+// entries: w(j) = hi[j / kTwSplit] * lo[j mod kTwSplit] (one rounding more
+// than a full table, whose 128 KB would not fit beside the data).
+constexpr int kTwSplit = 128;
+static_assert(kTwSplit * kTwSplit == kTwMax, "two-level twiddle table");
+
+struct TwLds {
+    float2 lo[kTwSplit], hi[kTwSplit];
+};
+
+__device__ inline void load_twiddles(TwLds &t, const float2 *__restrict__ tw)
+{
+    for (int j = threadIdx.x; j < kTwSplit; j += blockDim.x) {
+        t.lo[j] = tw[j];
+        t.hi[j] = tw[j * kTwSplit];
+    }
+}
+
+__device__ inline float2 twiddle(const TwLds &t, int j)
+{
+    return cmul(t.hi[j >> 7], t.lo[j & (kTwSplit - 1)]);
+}
+
 // Stockham autosort FFT over `batch` transforms of length N = 2^log2N stored
 // back to back in LDS (batch * N <= NT * Q4 * 4): radix-4 stages, then one
 // radix-2 stage when log2N is odd. Stage with sub-length Ns and radix R:
@@ -32,7 +55,7 @@ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x
 // inputs in registers across a barrier, so input and output share the buffer.
 // INV: the inverse transform (conjugate twiddles, no 1/N scaling).
 template <int NT, int Q4, bool INV>
-__device__ void fft_lds(float2 *buf, int log2N, int batch, const float2 *__restrict__ tw)
+__device__ void fft_lds(float2 *buf, int log2N, int batch, const TwLds &tw)
 {
     const int tid = threadIdx.x;
     const int N = 1 << log2N;
@@ -62,7 +85,8 @@ __device__ void fft_lds(float2 *buf, int log2N, int batch, const float2 *__restr
             if (j < nb) {
                 const int b = j >> (log2N - 2), jj = j & (quarter - 1);
                 const int k = jj & (Ns - 1);
-                const float2 w1 = tw[k * step], w2 = tw[2 * k * step], w3 = tw[3 * k * step];
+                const float2 w1 = twiddle(tw, k * step);
+                const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
                 const float2 a0 = v[q][0];
                 const float2 a1 = INV ? cmulconj(v[q][1], w1) : cmul(v[q][1], w1);
                 const float2 a2 = INV ? cmulconj(v[q][2], w2) : cmul(v[q][2], w2);
@@ -101,7 +125,7 @@ __device__ void fft_lds(float2 *buf, int log2N, int batch, const float2 *__restr
             const int j = tid + q * NT;
             if (j < nb) {
                 const int b = j >> (log2N - 1), k = j & (half - 1);
-                const float2 w = tw[k * step];
+                const float2 w = twiddle(tw, k * step);
                 const float2 a1 = INV ? cmulconj(v[q][1], w) : cmul(v[q][1], w);
                 float2 *dst = buf + (b << log2N) + k;
                 dst[0] = cadd(v[q][0], a1);
@@ -158,11 +182,13 @@ hipError_t launch_an_transpose(const AnChunk &a, int max_n, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------- Welch
-// One workgroup per region: each segment's mean is taken of its deviations
-// from its first sample (a constant segment detrends to exact zeros); then
-// batches of whole segments are detrended, windowed, transformed in LDS and
-// their squared magnitudes summed per bin (each bin owned by one thread, so
-// the sum runs over segments in order).
+// One workgroup per region. Each segment's mean is taken of its deviations
+// from its first sample (a constant segment detrends to exact zeros). Segments
+// 2p and 2p+1, detrended and windowed, form the real and imaginary parts of one
+// complex transform Z; for real segments a, b the summed periodogram is
+// |A_f|^2 + |B_f|^2 = (|Z_f|^2 + |Z_{L-f}|^2) / 2 (an odd last segment rides
+// alone, with the same identity). Batches of such transforms run in LDS; each
+// bin is owned by one thread, so the sum runs over segments in order.
 constexpr int kWelchBinsPerThread = (kMaxSegment / 2 + 1 + kWelchThreads - 1) / kWelchThreads;
 constexpr int kMaxSegments = 2 * kTwMax / kMinSegment;
 
@@ -170,11 +196,13 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
 {
     extern __shared__ float2 buf[];               // kWelchBatch complex values
     __shared__ float smean[kMaxSegments];         // mean deviation from the segment's first sample
+    __shared__ TwLds tw;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t g = blockIdx.x;
     const float *x = a.xT + g * a.Na;
     const int L = a.L, hop = L >> 1;
     const float invL = 1.f / (float)L;            // a power of two: exact
+    load_twiddles(tw, a.tw);
     for (int sg = wave; sg < a.n_seg; sg += kWelchThreads / 64) {
         const float *xs = x + sg * hop;
         const float ref = xs[0];
@@ -188,26 +216,36 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
     float acc[kWelchBinsPerThread];
 #pragma unroll
     for (int q = 0; q < kWelchBinsPerThread; ++q) acc[q] = 0.f;
-    const int per_batch = kWelchBatch >> a.log2L;
-    for (int s0 = 0; s0 < a.n_seg; s0 += per_batch) {
-        const int ns = min(per_batch, a.n_seg - s0);
-        for (int e = tid; e < (ns << a.log2L); e += kWelchThreads) {
-            const int sg = s0 + (e >> a.log2L), m = e & (L - 1);
-            const float *xs = x + sg * hop;
-            buf[e] = make_float2(((xs[m] - xs[0]) - smean[sg]) * a.hann[m], 0.f);
+    const int per_batch = kWelchBatch >> a.log2L;          // transforms per batch
+    const int n_pairs = (a.n_seg + 1) >> 1;
+    for (int p0 = 0; p0 < n_pairs; p0 += per_batch) {
+        const int np = min(per_batch, n_pairs - p0);
+        for (int e = tid; e < (np << a.log2L); e += kWelchThreads) {
+            const int p = p0 + (e >> a.log2L), m = e & (L - 1);
+            const int sa = 2 * p, sb = sa + 1;
+            const float w = a.hann[m];
+            const float *xa = x + sa * hop;
+            const float re = ((xa[m] - xa[0]) - smean[sa]) * w;
+            float im = 0.f;
+            if (sb < a.n_seg) {
+                const float *xb = x + sb * hop;
+                im = ((xb[m] - xb[0]) - smean[sb]) * w;
+            }
+            buf[e] = make_float2(re, im);
         }
         __syncthreads();
-        fft_lds<kWelchThreads, kWelchBatch / 4 / kWelchThreads, false>(buf, a.log2L, ns, a.tw);
+        fft_lds<kWelchThreads, kWelchBatch / 4 / kWelchThreads, false>(buf, a.log2L, np, tw);
 #pragma unroll
         for (int q = 0; q < kWelchBinsPerThread; ++q) {
             const int f = tid + q * kWelchThreads;
             if (f < nb2) {
-                float p = 0.f;
-                for (int sg = 0; sg < ns; ++sg) {
-                    const float2 X = buf[(sg << a.log2L) + f];
-                    p += X.x * X.x + X.y * X.y;
+                const int fm = (L - f) & (L - 1);
+                float pw = 0.f;
+                for (int t = 0; t < np; ++t) {
+                    const float2 Z1 = buf[(t << a.log2L) + f], Z2 = buf[(t << a.log2L) + fm];
+                    pw += 0.5f * ((Z1.x * Z1.x + Z1.y * Z1.y) + (Z2.x * Z2.x + Z2.y * Z2.y));
                 }
-                acc[q] += p;
+                acc[q] += pw;
             }
         }
         __syncthreads();
@@ -237,13 +275,15 @@ template <int Q4>
 __global__ __launch_bounds__(kHilbertThreads) void an_hilbert_kernel(AnChunk a)
 {
     extern __shared__ float2 buf[];               // Na complex values
+    __shared__ TwLds tw;
     const int tid = threadIdx.x;
     const int64_t g = blockIdx.x;
     const int N = a.Na;
     const float *x = a.xT + g * N;
+    load_twiddles(tw, a.tw);
     for (int t = tid; t < N; t += kHilbertThreads) buf[t] = make_float2(x[t], 0.f);
     __syncthreads();
-    fft_lds<kHilbertThreads, Q4, false>(buf, a.log2Na, 1, a.tw);
+    fft_lds<kHilbertThreads, Q4, false>(buf, a.log2Na, 1, tw);
     const int half = N >> 1;
     for (int f = tid; f < N; f += kHilbertThreads) {
         const float h = (f == 0 || f > half) ? 0.f : (f == half ? 1.f : 2.f);
@@ -251,7 +291,7 @@ __global__ __launch_bounds__(kHilbertThreads) void an_hilbert_kernel(AnChunk a)
         buf[f] = make_float2(X.x * h, X.y * h);
     }
     __syncthreads();
-    fft_lds<kHilbertThreads, Q4, true>(buf, a.log2Na, 1, a.tw);
+    fft_lds<kHilbertThreads, Q4, true>(buf, a.log2Na, 1, tw);
     const float inv = 1.f / (float)N;             // a power of two: exact
     float2 *z = a.z + g * N;
     for (int t = tid; t < N; t += kHilbertThreads) {

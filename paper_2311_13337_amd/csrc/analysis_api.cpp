@@ -106,7 +106,8 @@ vadx_status analysis_bytes(int64_t n_samples, int32_t n_max, int64_t regions_per
 
 vadx_status run_analysis(int device, hipStream_t stream, const AnInstances &in, double period_ms,
                          const vadx_analysis_cfg *cfg, void *ws, size_t ws_bytes,
-                         vadx_analysis *out, float *psd_out, float *pli_out, std::string &err)
+                         vadx_analysis *out, float *psd_out, float *pli_out, AnTimer *timer,
+                         std::string &err)
 {
     if (!ws || ((uintptr_t)ws & 255u) || !out || !in.samples) {
         err = "null or misaligned pointer";
@@ -237,12 +238,24 @@ vadx_status run_analysis(int device, hipStream_t stream, const AnInstances &in, 
         a.pli_passes = pli_passes(cmax);
         a.pli_tc = pli_time_chunk(cmax, r.Na);
         a.out = out + i0;
-        AN_TRY(launch_an_transpose(a, cmax, stream));
-        AN_TRY(launch_an_welch(a, stream));
-        AN_TRY(launch_an_hilbert(a, stream));
-        AN_TRY(launch_an_pli(a, cmax, stream));
-        AN_TRY(launch_an_ud(a, stream));
-        AN_TRY(launch_an_final(a, stream));
+        for (int kk = 0; kk < kAnKernels; ++kk) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timer) {
+                AN_TRY(hipEventCreate(&e0));
+                AN_TRY(hipEventCreate(&e1));
+                timer->ev[kk].emplace_back(e0, e1);
+                AN_TRY(hipEventRecord(e0, stream));
+            }
+            switch (kk) {
+            case 0: AN_TRY(launch_an_transpose(a, cmax, stream)); break;
+            case 1: AN_TRY(launch_an_welch(a, stream)); break;
+            case 2: AN_TRY(launch_an_hilbert(a, stream)); break;
+            case 3: AN_TRY(launch_an_pli(a, cmax, stream)); break;
+            case 4: AN_TRY(launch_an_ud(a, stream)); break;
+            default: AN_TRY(launch_an_final(a, stream)); break;
+            }
+            if (timer) AN_TRY(hipEventRecord(e1, stream));
+        }
         if (psd_out)
             AN_TRY(hipMemcpyAsync(psd_out + reg_done * r.nb2, d_psd, sizeof(float) * regs * r.nb2,
                                   hipMemcpyDeviceToDevice, stream));

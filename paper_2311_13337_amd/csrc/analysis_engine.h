@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "vadx.h"
 
@@ -16,7 +18,7 @@ namespace vadx {
 constexpr int kTwMax = 16384;
 // Welch segments are transformed kWelchBatch complex values at a time (LDS).
 constexpr int kWelchBatch = 8192;
-constexpr int kWelchThreads = 256;
+constexpr int kWelchThreads = 512;
 constexpr int kHilbertThreads = 512;
 constexpr int kPliThreads = 256;
 constexpr int kUdThreads = 256;
@@ -67,6 +69,15 @@ hipError_t launch_an_final(const AnChunk &a, hipStream_t s);
 int pli_time_chunk(int n, int Na);
 int pli_passes(int n);
 
+// Optional per-kernel timing of the analysis launches (HIP events on the
+// launch stream): transpose, Welch, analytic signal, PLI, Up/Down, final.
+constexpr int kAnKernels = 6;
+struct AnTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kAnKernels];
+    int64_t n[kAnKernels] = {};
+    double ms[kAnKernels] = {};
+};
+
 // Host driver shared by the two entry points: instances given by their
 // sample offsets (floats from `samples`) and region counts.
 struct AnInstances {
@@ -78,7 +89,8 @@ struct AnInstances {
 };
 vadx_status run_analysis(int device, hipStream_t stream, const AnInstances &in, double period_ms,
                          const vadx_analysis_cfg *cfg, void *ws, size_t ws_bytes,
-                         vadx_analysis *out, float *psd_out, float *pli_out, std::string &err);
+                         vadx_analysis *out, float *psd_out, float *pli_out, AnTimer *timer,
+                         std::string &err);
 vadx_status analysis_bytes(int64_t n_samples, int32_t n_max, int64_t regions_per_pass,
                            const vadx_analysis_cfg *cfg, size_t *bytes, std::string &err);
 

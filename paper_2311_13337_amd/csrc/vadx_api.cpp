@@ -111,6 +111,7 @@ struct vadx_ctx {
     int64_t n_int = 0, n_fc = 0;
     double ms_int = 0.0, ms_fc = 0.0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_int, ev_fc;
+    AnTimer an_timer;                    // analysis launches (when timing is on)
     // launch shape: 0 = persistent work queue (default), 1 = one workgroup per group
     int launch_mode = 0;
     // graph replay of whole runs
@@ -212,6 +213,8 @@ void vadx_destroy(vadx_ctx *c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &e : c->ev_int) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto &e : c->ev_fc) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto &v : c->an_timer.ev)
+        for (auto &e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     c->rowptr.release(); c->colidx.release(); c->weight.release(); c->edge_len.release();
     c->sc.release(); c->d_conns.release(); c->d_inst.release(); c->d_perm.release();
     c->d_groups.release(); c->d_tables.release(); c->d_packed.release();
@@ -1085,7 +1088,7 @@ extern "C" vadx_status vadx_analyze_series(vadx_ctx *c, const float *samples, in
     AnInstances in{samples, off.data(), ns.data(), n_inst, n_samples};
     std::string err;
     vadx_status st = run_analysis(c->device, c->stream, in, sample_period_ms, cfg, ws, ws_bytes, out,
-                                  psd_out, pli_out, err);
+                                  psd_out, pli_out, c->timing ? &c->an_timer : nullptr, err);
     if (st) return fail(c, st, "%s", err.c_str());
     return VADX_OK;
 }
@@ -1106,7 +1109,22 @@ extern "C" vadx_status vadx_analyze(vadx_ctx *c, const vadx_analysis_cfg *cfg, v
     const double period = (double)c->plan_run.tavg_steps * c->plan_run.dt_ms;
     std::string err;
     vadx_status st = run_analysis(c->device, c->stream, in, period, cfg, ws, ws_bytes, out, nullptr,
-                                  nullptr, err);
+                                  nullptr, c->timing ? &c->an_timer : nullptr, err);
     if (st) return fail(c, st, "%s", err.c_str());
+    return VADX_OK;
+}
+
+extern "C" vadx_status vadx_analysis_kernel_time(vadx_ctx *c, int64_t *launches, double *ms)
+{
+    if (!c || !launches || !ms) return fail(c, VADX_E_ARG, "null argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (int k = 0; k < kAnKernels; ++k) {
+        vadx_status st = drain(c, c->an_timer.ev[k], c->an_timer.n[k], c->an_timer.ms[k]);
+        if (st) return st;
+        launches[k] = c->an_timer.n[k];
+        ms[k] = c->an_timer.ms[k];
+        c->an_timer.n[k] = 0;
+        c->an_timer.ms[k] = 0.0;
+    }
     return VADX_OK;
 }

@@ -32,7 +32,10 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
-           "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze")
+           "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze",
+           "vadx_analysis_kernel_time")
+ANALYSIS_KERNELS = ("an_transpose_kernel", "an_welch_kernel", "an_hilbert_kernel", "an_pli_kernel",
+                    "an_ud_kernel", "an_final_kernel")
 ANALYSIS_NAMES = ("psd_fmax_hz", "psd_ampmax", "psd_slope_a", "psd_log10_b", "mean_pli",
                   "ud_up_ms", "ud_down_ms")
 MLP_PARAMS = 17926
@@ -149,6 +152,7 @@ def lib():
             "vadx_analyze_series": (st, [vp, vp, C.c_int64, C.c_int32, C.c_int64, C.c_double,
                                          P(vadx_analysis_cfg), vp, C.c_size_t, vp, vp, vp]),
             "vadx_analyze": (st, [vp, P(vadx_analysis_cfg), vp, C.c_size_t, vp]),
+            "vadx_analysis_kernel_time": (st, [vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -323,6 +327,14 @@ class Context:
     def vadx_analyze(self, cfg: "vadx_analysis_cfg", ws, out):
         self._check(lib().vadx_analyze(self.h, C.byref(cfg), C.c_void_p(ws.data_ptr()),
                                        ws.numel() * ws.element_size(), C.c_void_p(out.data_ptr())))
+
+
+def analysis_kernel_time(ctx: "Context"):
+    """{kernel: (launches, ms)} of the analysis launches since the last call."""
+    n = np.zeros(6, np.int64)
+    ms = np.zeros(6, np.float64)
+    ctx._check(lib().vadx_analysis_kernel_time(ctx.h, _ptr(n), _ptr(ms)))
+    return {k: (int(a), float(b)) for k, a, b in zip(ANALYSIS_KERNELS, n, ms)}
 
 
 def vadx_analysis_defaults() -> vadx_analysis_cfg:

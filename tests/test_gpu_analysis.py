@@ -63,7 +63,8 @@ def _check(g, psd_g, pli_g, o, tag):
     tot = P.sum(axis=1, keepdims=True)
     err = np.abs(psd_g.astype(np.float64) - P)
     lim = 1e-4 * P + 1e-6 * tot
-    assert np.all(err <= lim), (tag, "psd", float((err / np.maximum(lim, 1e-300)).max()))
+    r_psd = float((err / np.maximum(lim, 1e-300)).max())
+    assert np.all(err <= lim), (tag, "psd", r_psd)
     # peak of the region-mean spectrum
     M = o["mean_psd"]
     Mtot = M.sum()
@@ -92,6 +93,11 @@ def _check(g, psd_g, pli_g, o, tag):
     assert int(g["ud_down_samples"]) == o["ud_down_sum"], tag
     assert g["ud_up_ms"] == pytest.approx(o["ud_up_ms"], rel=1e-6, abs=1e-12)
     assert g["ud_down_ms"] == pytest.approx(o["ud_down_ms"], rel=1e-6, abs=1e-12)
+    print(f"[analysis] {tag}: psd err/tol max {r_psd:.3g}; slope err "
+          f"{abs(g['psd_slope_a'] - o['psd_slope_a']):.2e}; pli |d| max {dP.max():.2e} "
+          f"(ambiguous samples max {int(o['pli_ambiguous'].max())}); mean_pli "
+          f"{g['mean_pli']:.5f} vs {o['mean_pli']:.5f}; peak bin {b} vs {o['psd_peak_bin']}",
+          flush=True)
 
 
 @pytest.mark.parametrize("n_inst,n,ns,seed", [(4, 68, 9000, 11), (3, 5, 300, 12), (2, 84, 4500, 13),
@@ -181,3 +187,36 @@ def test_analyze_after_integration_matches_series():
     sw.ctx.vadx_analyze_series(S, ns, n, 1.0, cfg, ws, out2)
     torch.cuda.synchronize()
     assert out1.cpu().numpy().tobytes() == out2.cpu().numpy().tobytes()
+
+
+def test_analysis_full_size_sampled():
+    """The configuration bench.py times: 4096 instances x 68 regions x 9000
+    samples (window 8192, segments of 1024) in one pass. Sixteen distinct
+    synthetic instances are tiled 256 times; the sixteen are checked against the
+    oracle and every copy must give the bits of its original."""
+    import torch
+    base = inputs.synthetic_rate_series(16, 68, 9000, seed=41)
+    print("[analysis] full size 4096 x 68 x 9000", flush=True)
+    dev = torch.from_numpy(base).cuda().repeat(256, 1, 1)
+    n_inst, ns, n = dev.shape
+    cfg = vadx.vadx_analysis_defaults()
+    ctx = vadx.Context(0)
+    ws = torch.empty(vadx.vadx_analysis_ws_bytes(ns, n, n_inst * n, cfg), dtype=torch.uint8,
+                     device="cuda")
+    out = vadx.analysis_out(n_inst)
+    psd = torch.empty((n_inst, n, 513), dtype=torch.float32, device="cuda")
+    pli = torch.empty((n_inst, n, n), dtype=torch.float32, device="cuda")
+    ctx.vadx_analyze_series(dev, ns, n, 1.0, cfg, ws, out, psd, pli)
+    torch.cuda.synchronize()
+    del ws, dev
+    g = vadx.analysis_to_numpy(out)
+    raw = out.cpu().numpy().reshape(n_inst, -1)
+    psd_h = psd.cpu().numpy()
+    pli_h = pli.cpu().numpy()
+    for i in range(16, n_inst):
+        j = i % 16
+        assert raw[i].tobytes() == raw[j].tobytes(), i
+    assert np.array_equal(psd_h[16:].reshape(255, 16, n, 513), np.broadcast_to(psd_h[:16], (255, 16, n, 513)))
+    assert np.array_equal(pli_h[16:].reshape(255, 16, n, n), np.broadcast_to(pli_h[:16], (255, 16, n, n)))
+    for j in range(16):
+        _check(g[j], psd_h[j], pli_h[j], _oracle(base[j], 1.0, cfg), ("full", j))
