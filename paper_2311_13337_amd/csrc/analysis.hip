@@ -269,32 +269,65 @@ hipError_t launch_an_welch(const AnChunk &a, hipStream_t s)
 }
 
 // -------------------------------------------------------------------- Hilbert
-// One workgroup per region: DFT of the window, bin 0 and the negative bins
-// zeroed, bins 1..N/2-1 doubled, inverse DFT, scaled by 1/N.
+// One workgroup per region. The real window x (N samples) is transformed as
+// the complex sequence c_m = x_2m + i x_2m+1 of length M = N/2; with
+// E = (C_f + conj C_{M-f})/2 and O = (C_f - conj C_{M-f})/(2i) (the transforms
+// of the even and odd samples), X_f = E + W^f O and X_{M-f} = conj(E - W^f O),
+// W = exp(-2 pi i / N). The analytic weights are applied on the way (bin 0 to
+// zero, bins 1..M-1 doubled, bin M kept, bins above M zero), then the inverse
+// transform of length N, scaled by 1/N.
 template <int Q4>
 __global__ __launch_bounds__(kHilbertThreads) void an_hilbert_kernel(AnChunk a)
 {
     extern __shared__ float2 buf[];               // Na complex values
     __shared__ TwLds tw;
+    constexpr int NT = kHilbertThreads;
+    constexpr int PM = (kTwMax / 4 + 1 + NT - 1) / NT;   // bin pairs per thread
     const int tid = threadIdx.x;
     const int64_t g = blockIdx.x;
-    const int N = a.Na;
+    const int N = a.Na, M = N >> 1;
     const float *x = a.xT + g * N;
     load_twiddles(tw, a.tw);
-    for (int t = tid; t < N; t += kHilbertThreads) buf[t] = make_float2(x[t], 0.f);
+    for (int m = tid; m < M; m += NT) buf[m] = make_float2(x[2 * m], x[2 * m + 1]);
     __syncthreads();
-    fft_lds<kHilbertThreads, Q4, false>(buf, a.log2Na, 1, tw);
-    const int half = N >> 1;
-    for (int f = tid; f < N; f += kHilbertThreads) {
-        const float h = (f == 0 || f > half) ? 0.f : (f == half ? 1.f : 2.f);
-        const float2 X = buf[f];
-        buf[f] = make_float2(X.x * h, X.y * h);
+    fft_lds<NT, Q4, false>(buf, a.log2Na - 1, 1, tw);
+    float2 ca[PM], cb[PM];
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+        const int f = tid + q * NT;
+        if (f <= (M >> 1)) {
+            ca[q] = buf[f];
+            cb[q] = buf[(M - f) & (M - 1)];
+        }
     }
     __syncthreads();
-    fft_lds<kHilbertThreads, Q4, true>(buf, a.log2Na, 1, tw);
+    const int tstep = kTwMax >> a.log2Na;
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+        const int f = tid + q * NT;
+        if (f <= (M >> 1)) {
+            const float2 A = ca[q], B = cb[q];
+            const float2 E = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+            const float2 O = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));
+            const float2 WO = cmul(twiddle(tw, f * tstep), O);
+            const float2 Xf = cadd(E, WO);
+            const float2 Dg = csub(E, WO);
+            const float2 Xg = make_float2(Dg.x, -Dg.y);
+            if (f == 0) {
+                buf[0] = make_float2(0.f, 0.f);
+                buf[M] = Xg;
+            } else {
+                buf[f] = make_float2(2.f * Xf.x, 2.f * Xf.y);
+                if (M - f != f) buf[M - f] = make_float2(2.f * Xg.x, 2.f * Xg.y);
+            }
+        }
+    }
+    for (int t = M + 1 + tid; t < N; t += NT) buf[t] = make_float2(0.f, 0.f);
+    __syncthreads();
+    fft_lds<NT, Q4, true>(buf, a.log2Na, 1, tw);
     const float inv = 1.f / (float)N;             // a power of two: exact
     float2 *z = a.z + g * N;
-    for (int t = tid; t < N; t += kHilbertThreads) {
+    for (int t = tid; t < N; t += NT) {
         const float2 v = buf[t];
         z[t] = make_float2(v.x * inv, v.y * inv);
     }
@@ -326,7 +359,10 @@ hipError_t launch_an_hilbert(const AnChunk &a, hipStream_t s)
 // (bk, bl), bk <= bl); workgroup `pass` takes tiles pass*NT .. pass*NT+NT-1,
 // one per thread. The analytic signals of all regions are staged through LDS
 // tc samples at a time ([k][tc + 1] layout). Each pair accumulates
-// sign(Im(z_k conj z_l)) = sign(y_k x_l - x_k y_l) as an integer.
+// sign(Im(z_k conj z_l)) = sign(y_k x_l - x_k y_l): with z_k scaled by 2^100
+// (no overflow for |z| < 1e4), clamping the scaled value to [-1, 1] gives the
+// sign for every |Im| >= 2^-100 and 0 for Im = 0, so one clamp replaces two
+// compares; the sum of +-1 stays exact in single precision (|sum| <= 16384).
 int pli_time_chunk(int n, int Na)
 {
     int tc = 64;
@@ -358,11 +394,12 @@ __global__ __launch_bounds__(kPliThreads) void an_pli_kernel(AnChunk a)
     const int tc = a.pli_tc, ld = tc + 1;
     const int64_t rb = a.rbase[i];
     const float2 *z = a.z + rb * a.Na;
-    int acc[4][4];
+    float acc[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+        for (int q = 0; q < 4; ++q) acc[p][q] = 0.f;
+    const float kScale = 0x1p100f;
     const int k0 = 4 * bk, l0 = 4 * bl;
     // rows beyond n read row n-1 (their pairs are masked out below)
     int kr[4], lr[4];
@@ -378,11 +415,13 @@ __global__ __launch_bounds__(kPliThreads) void an_pli_kernel(AnChunk a)
         }
         __syncthreads();
         if (active) {
+#pragma unroll 4
             for (int tt = 0; tt < tc; ++tt) {
                 float2 zk[4], zl[4];
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    zk[p] = zs[kr[p] + tt];
+                    const float2 v = zs[kr[p] + tt];
+                    zk[p] = make_float2(v.x * kScale, v.y * kScale);
                     zl[p] = zs[lr[p] + tt];
                 }
 #pragma unroll
@@ -390,7 +429,7 @@ __global__ __launch_bounds__(kPliThreads) void an_pli_kernel(AnChunk a)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const float im = zk[p].y * zl[q].x - zk[p].x * zl[q].y;
-                        acc[p][q] += (im > 0.f) - (im < 0.f);
+                        acc[p][q] += __builtin_amdgcn_fmed3f(im, -1.f, 1.f);
                     }
             }
         }
@@ -407,7 +446,7 @@ __global__ __launch_bounds__(kPliThreads) void an_pli_kernel(AnChunk a)
             for (int q = 0; q < 4; ++q) {
                 const int k = k0 + p, l = l0 + q;
                 if (k < n && l < n && k <= l) {
-                    const float v = k < l ? (float)abs(acc[p][q]) * invN : 0.f;
+                    const float v = k < l ? fabsf(acc[p][q]) * invN : 0.f;
                     if (k < l) part += v;
                     if (M) {
                         M[(int64_t)k * n + l] = v;
