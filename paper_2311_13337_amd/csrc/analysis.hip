@@ -207,6 +207,7 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
         const float *xs = x + sg * hop;
         const float ref = xs[0];
         float s = 0.f;
+#pragma unroll 4
         for (int m = lane; m < L; m += 64) s += xs[m] - ref;
         s = wave_sum(s);
         if (lane == 0) smean[sg] = s * invL;
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
     const int n_pairs = (a.n_seg + 1) >> 1;
     for (int p0 = 0; p0 < n_pairs; p0 += per_batch) {
         const int np = min(per_batch, n_pairs - p0);
+#pragma unroll 4
         for (int e = tid; e < (np << a.log2L); e += kWelchThreads) {
             const int p = p0 + (e >> a.log2L), m = e & (L - 1);
             const int sa = 2 * p, sb = sa + 1;
