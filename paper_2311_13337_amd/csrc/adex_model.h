@@ -13,9 +13,12 @@
 // tau_N = tau_V g_L/C_m; threshold = quadratic polynomial (Table 1) of the
 // normalised (mu_V, sigma_V, tau_N); F = erfc((V_thre - mu_V)/(sqrt2 sigma_V))
 // / (2 tau_V). The value and the exact first and second derivatives in
-// (xe, xi) are carried as 6-component jets; the derivatives of every quantity
-// that depends on the inputs only through G are formed from its scalar
-// derivatives in G, and mu_V's derivatives from its closed form.
+// (xe, xi) enter eq. 1 only through the gradient and through the Hessian's
+// contraction with the covariance matrix C of the inputs, q = tr(C H) / 2, so
+// every quantity is carried as a 4-component jet (value, gradient, q): the
+// product and chain rules hold for q with the bilinear term grad x . C grad y.
+// The derivatives of every quantity that depends on the inputs only through G
+// are formed from its scalar derivatives in G, and mu_V's from its closed form.
 //
 // Drift (Section 2.1, eq. 1-3) and OU (eq. 4): see step_region().
 #pragma once
@@ -48,6 +51,7 @@ struct KModel {
     float P0[2];
     float plin[2][3];
     float Hraw[2][6];           // 00 01 02 11 12 22
+    float Hq[2][6];             // Hraw with the diagonal halved: sum Hq_kl M_kl over k <= l = sum_kl H_kl M_kl / 2
     float pc[3];
     float invT, invNe, invNi;
     float inv_tauw[2], b_i, a_i;
@@ -66,8 +70,13 @@ inline int model_variant(const KModel &M)
     return (M.tau_e == M.tau_i ? kVarEq : 0) | (M.same_inputs ? kVarSame : 0);
 }
 
-// A value with its gradient (a = d/dxe, b = d/dxi) and Hessian.
-template <class T> struct Jet { T v, a, b, aa, ab, bb; };
+// A value with its gradient (a = d/dxe, b = d/dxi) and q = tr(C H) / 2, H its
+// Hessian in (xe, xi), C the covariance matrix of (xe, xi).
+template <class T> struct QJet { T v, a, b, q; };
+
+// Covariance matrix C of the inputs (C_ee, C_ei, C_ii) and its products with
+// n = (a_e, a_i), the gradient direction of G: (nx, ny) = C n, qG = n . C n / 2.
+template <class T> struct Cov { T ee, ei, ii, nx, ny, qG; };
 
 // ---------------------------------------------------------------- primitives
 // The scalar primitives a type must provide (float overloads below):
@@ -123,71 +132,42 @@ VADX_HD float selectf(bool c, float a, float b) { return c ? a : b; }
 VADX_HD float maxf_(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // ---------------------------------------------------------------- jet algebra
-template <class T> VADX_HD Jet<T> jmul(const Jet<T> &x, const Jet<T> &y)
+// grad x . C grad y
+template <class T> VADX_HD T cdot(const Cov<T> &C, T xa, T xb, T ya, T yb)
 {
-    Jet<T> r;
+    return fmaf_(xa, fmaf_(C.ee, ya, C.ei * yb), xb * fmaf_(C.ei, ya, C.ii * yb));
+}
+// C grad x
+template <class T> VADX_HD void cvec(const Cov<T> &C, T xa, T xb, T &cx, T &cy)
+{
+    cx = fmaf_(C.ee, xa, C.ei * xb);
+    cy = fmaf_(C.ei, xa, C.ii * xb);
+}
+template <class T> VADX_HD QJet<T> qmul(const QJet<T> &x, const QJet<T> &y, const Cov<T> &C)
+{
+    QJet<T> r;
     r.v = x.v * y.v;
     r.a = fmaf_(x.a, y.v, x.v * y.a);
     r.b = fmaf_(x.b, y.v, x.v * y.b);
-    r.aa = fmaf_(x.aa, y.v, fmaf_(T(2) * x.a, y.a, x.v * y.aa));
-    r.ab = fmaf_(x.ab, y.v, fmaf_(x.a, y.b, fmaf_(x.b, y.a, x.v * y.ab)));
-    r.bb = fmaf_(x.bb, y.v, fmaf_(T(2) * x.b, y.b, x.v * y.bb));
+    r.q = fmaf_(x.q, y.v, fmaf_(x.v, y.q, cdot(C, x.a, x.b, y.a, y.b)));
     return r;
 }
-template <class T> VADX_HD Jet<T> jsq(const Jet<T> &x)
+template <class T> VADX_HD QJet<T> qadd(const QJet<T> &x, const QJet<T> &y)
 {
-    Jet<T> r;
-    T v2 = T(2) * x.v;
-    r.v = x.v * x.v;
-    r.a = v2 * x.a;
-    r.b = v2 * x.b;
-    r.aa = fmaf_(v2, x.aa, T(2) * x.a * x.a);
-    r.ab = fmaf_(v2, x.ab, T(2) * x.a * x.b);
-    r.bb = fmaf_(v2, x.bb, T(2) * x.b * x.b);
-    return r;
+    return QJet<T>{x.v + y.v, x.a + y.a, x.b + y.b, x.q + y.q};
 }
-template <class T> VADX_HD Jet<T> jadd(const Jet<T> &x, const Jet<T> &y)
+// f(x) given f, f', f'' at x.v: q = f' q_x + f'' (grad x . C grad x) / 2
+template <class T> VADX_HD QJet<T> qchain(const QJet<T> &x, T f0, T f1, T f2, const Cov<T> &C)
 {
-    return Jet<T>{x.v + y.v, x.a + y.a, x.b + y.b, x.aa + y.aa, x.ab + y.ab, x.bb + y.bb};
-}
-// s*x + c
-template <class T> VADX_HD Jet<T> jaffine(const Jet<T> &x, T s, T c)
-{
-    return Jet<T>{fmaf_(s, x.v, c), s * x.a, s * x.b, s * x.aa, s * x.ab, s * x.bb};
-}
-// f(x) given f, f', f'' at x.v (chain rule to second order)
-template <class T> VADX_HD Jet<T> jchain(const Jet<T> &x, T f0, T f1, T f2)
-{
-    Jet<T> r;
-    r.v = f0;
-    r.a = f1 * x.a;
-    r.b = f1 * x.b;
-    T fa = f2 * x.a;
-    r.aa = fmaf_(f1, x.aa, fa * x.a);
-    r.ab = fmaf_(f1, x.ab, fa * x.b);
-    r.bb = fmaf_(f1, x.bb, f2 * x.b * x.b);
-    return r;
+    T cx, cy;
+    cvec(C, x.a, x.b, cx, cy);
+    const T half_quad = T(0.5f) * fmaf_(x.a, cx, x.b * cy);
+    return QJet<T>{f0, f1 * x.a, f1 * x.b, fmaf_(f1, x.q, f2 * half_quad)};
 }
 // a function of G = g_L + aE xe + aI xi only: f, f', f'' in G
-template <class T> VADX_HD Jet<T> jofG(T f0, T f1, T f2, T aE, T aI)
+template <class T> VADX_HD QJet<T> qofG(T f0, T f1, T f2, T aE, T aI, const Cov<T> &C)
 {
-    T f2e = f2 * aE;
-    return Jet<T>{f0, f1 * aE, f1 * aI, f2e * aE, f2e * aI, f2 * aI * aI};
-}
-
-// x * f(G) for f known through f, f', f'' in G (aEE = aE^2, aEI = aE aI, aII = aI^2)
-template <class T>
-VADX_HD Jet<T> jmulG(const Jet<T> &x, T f0, T f1, T f2, T aE, T aI, T aEE, T aEI, T aII)
-{
-    T fa = f1 * aE, fb = f1 * aI, v2 = x.v * f2;
-    Jet<T> r;
-    r.v = x.v * f0;
-    r.a = fmaf_(x.a, f0, x.v * fa);
-    r.b = fmaf_(x.b, f0, x.v * fb);
-    r.aa = fmaf_(x.aa, f0, fmaf_(T(2) * x.a, fa, v2 * aEE));
-    r.ab = fmaf_(x.ab, f0, fmaf_(x.a, fb, fmaf_(x.b, fa, v2 * aEI)));
-    r.bb = fmaf_(x.bb, f0, fmaf_(T(2) * x.b, fb, v2 * aII));
-    return r;
+    return QJet<T>{f0, f1 * aE, f1 * aI, f2 * C.qG};
 }
 
 // erfc with a shared exp(-z^2): Numerical Recipes' Chebyshev fit
@@ -214,23 +194,26 @@ template <class T> VADX_HD void erfc_and_gauss(T z, T &g, T &e)
     g = selectf(z >= T(0), g_pos, T(2) - g_pos);
 }
 
-// Transfer function of population `pop` with its value and derivatives in
-// (xe, xi). Also returns mu_V (value) for the adaptation equation.
-// EQ: tau_e == tau_i, so d_i = d_e, 1/tau_V = d_e and sigma_V^2 = (A_e + A_i) d_e / 2.
 // The parts of the transfer function that depend on the inputs only through
-// xe, xi and G = g_L + a_e xe + a_i xi, not on the population: shared by the
-// two populations when their inputs coincide.
+// xe, xi, G = g_L + a_e xe + a_i xi and the input covariance, not on the
+// population: shared by the two populations when their inputs coincide.
+// EQ: tau_e == tau_i, so d_i = d_e, 1/tau_V = d_e and sigma_V^2 = (A_e + A_i) d_e / 2.
 template <class T> struct TFShared {
     T xe, xi, r, r2, r3;
     T de, he1, he2;             // d_e = 1/(C_m/G + tau_e) and its first two derivatives in G
     T cexe, cixi;               // c_e xe, c_i xi
-    // tau_e == tau_i only: phi = d_e / G^4 with its derivatives in G, and the
-    // jets of 1/tau_V = d_e and tau_V = C_m/G + tau_e
-    T phi, phi1, phi2;
-    Jet<T> ITV, TV;
+    T pq0;                      // the xe, xi terms of q(Pi): (C_ee c_i 2bI^2 xi + C_ii c_e 2bE^2 xe) / 2
+    // tau_e == tau_i only: phi = d_e / G^4 and the G-derivative terms of
+    // S2 = Pi phi; the jets of 1/tau_V = d_e and tau_V = C_m/G + tau_e and the
+    // C-products of their gradients
+    T phi, phi1aE, phi1aI, phi1nx, phi1ny, phi2qG;
+    QJet<T> ITV, TV;
+    T itv1nx, itv1ny, itv2qG;   // d_e' (C n), d_e'' qG
+    T tv1nx, tv1ny, m22;        // tau_V' (C n), grad tau_V . C grad tau_V
 };
 
-template <bool EQ, class T> VADX_HD TFShared<T> tf_shared(const KModel &M, T xe, T xi)
+template <bool EQ, class T>
+VADX_HD TFShared<T> tf_shared(const KModel &M, T xe, T xi, const Cov<T> &C)
 {
     TFShared<T> g;
     const T aE = T(M.aE), aI = T(M.aI);
@@ -247,38 +230,53 @@ template <bool EQ, class T> VADX_HD TFShared<T> tf_shared(const KModel &M, T xe,
     g.he2 = T(-2) * T(M.tau_e) * g.he1 * qe;
     g.cexe = T(M.ce) * xe;
     g.cixi = T(M.ci) * xi;
+    g.pq0 = T(0.5f) * fmaf_(C.ee * T(M.ci2bI2), xi, C.ii * T(M.ce2bE2) * xe);
     if constexpr (EQ) {
         // (ln phi)' = -(3 + tau d_e)/G, phi'' = phi (12 + 6 tau d_e + 2 (tau d_e)^2) / G^2
         T td = T(M.tau_e) * g.de;
         g.phi = g.r2 * g.r2 * g.de;
-        g.phi1 = -g.phi * g.r * (T(3) + td);
-        g.phi2 = g.phi * g.r2 * fmaf_(td, fmaf_(T(2), td, T(6)), T(12));
-        g.ITV = jofG(g.de, g.he1, g.he2, aE, aI);
+        const T phi1 = -g.phi * g.r * (T(3) + td);
+        const T phi2 = g.phi * g.r2 * fmaf_(td, fmaf_(T(2), td, T(6)), T(12));
+        g.phi1aE = phi1 * aE;
+        g.phi1aI = phi1 * aI;
+        g.phi1nx = phi1 * C.nx;
+        g.phi1ny = phi1 * C.ny;
+        g.phi2qG = phi2 * C.qG;
+        g.ITV = qofG(g.de, g.he1, g.he2, aE, aI, C);
+        g.itv1nx = g.he1 * C.nx;
+        g.itv1ny = g.he1 * C.ny;
+        g.itv2qG = g.ITV.q;
         // tau_V = T_eff + tau_e = C_m/G + tau_e
-        g.TV = jofG(fmaf_(T(M.Cm), g.r, T(M.tau_e)), -T(M.Cm) * g.r2, T(2) * T(M.Cm) * g.r3, aE, aI);
+        const T tv1 = -T(M.Cm) * g.r2;
+        g.TV = qofG(fmaf_(T(M.Cm), g.r, T(M.tau_e)), tv1, T(2) * T(M.Cm) * g.r3, aE, aI, C);
+        g.tv1nx = tv1 * C.nx;
+        g.tv1ny = tv1 * C.ny;
+        g.m22 = T(2) * tv1 * tv1 * C.qG;
     }
     return g;
 }
 
+// Transfer function of population `pop` with its gradient and q in (xe, xi).
+// Also returns mu_V (value) for the adaptation equation.
 template <bool EQ, class T>
-VADX_HD Jet<T> transfer(const KModel &M, int pop, const TFShared<T> &g, T W, T &muV_out)
+VADX_HD QJet<T> transfer(const KModel &M, int pop, const TFShared<T> &g, const Cov<T> &C, T W,
+                         T &muV_out)
 {
     const T aE = T(M.aE), aI = T(M.aI);
     const T xe = g.xe, xi = g.xi, r = g.r, r2 = g.r2, r3 = g.r3;
-    const T de = g.de, he1 = g.he1, he2 = g.he2;
     // mu_V through A = (E_e - mu_V) G = alpha_e + beta_e xi (linear in xi) and
-    // B = (E_i - mu_V) G = alpha_i + beta_i xe (linear in xe): mu_V = E_e - A/G
+    // B = (E_i - mu_V) G = alpha_i + beta_i xe (linear in xe): mu_V = E_e - A/G,
+    // Hessian -2A/G^3 n n^T + (bE/G^2)(n e_i^T + e_i n^T), so
+    // q = -2A/G^3 qG + bE/G^2 (C n)_i
     T c0 = T(M.gLEL[pop]) - W;
     T A = fmaf_(T(M.bE), xi, T(M.EegL) - c0);
     T B = fmaf_(T(M.bI), xe, T(M.EigL) - c0);
     T Ar2 = A * r2, Ar3 = T(2) * A * r3, bEr2 = T(M.bE) * r2;
-    Jet<T> MU;
+    QJet<T> MU;
     MU.v = fmaf_(-A, r, T(M.Ee));
     MU.a = Ar2 * aE;
     MU.b = fmaf_(Ar2, aI, -T(M.bE) * r);
-    MU.aa = -Ar3 * T(M.aEE);
-    MU.ab = fmaf_(bEr2, aE, -Ar3 * T(M.aEI));
-    MU.bb = fmaf_(T(2) * bEr2, aI, -Ar3 * T(M.aII));
+    MU.q = fmaf_(bEr2, C.ny, -Ar3 * C.qG);
     muV_out = MU.v;
     // shot-noise weights A_s = K_s x_s (tau_s U_s)^2 with U_e = Q_e A/G^2,
     // U_i = Q_i B/G^2: A_e + A_i = Pi / G^4 with the cubic
@@ -287,93 +285,121 @@ VADX_HD Jet<T> transfer(const KModel &M, int pop, const TFShared<T> &g, T W, T &
     const T ce = T(M.ce), ci = T(M.ci);
     const T cexe = g.cexe, cixi = g.cixi;
     T A2 = A * A, B2 = B * B;
-    Jet<T> PI;
-    PI.v = fmaf_(cexe, A2, cixi * B2);
-    PI.a = fmaf_(ce, A2, T(M.ci2bI) * xi * B);
-    PI.b = fmaf_(T(M.ce2bE) * xe, A, ci * B2);
-    PI.aa = T(M.ci2bI2) * xi;
-    PI.ab = fmaf_(T(M.ce2bE), A, T(M.ci2bI) * B);
-    PI.bb = T(M.ce2bE2) * xe;
-    Jet<T> S2, ITV, TV;                              // 2 sigma_V^2, 1/tau_V, tau_V
+    QJet<T> S2, ITV, TV;                             // 2 sigma_V^2, 1/tau_V, tau_V
     if constexpr (EQ) {
-        // S2 = Pi phi(G), phi = d_e / G^4
-        S2 = jmulG(PI, g.phi, g.phi1, g.phi2, aE, aI, T(M.aEE), T(M.aEI), T(M.aII));
+        QJet<T> PI;
+        PI.v = fmaf_(cexe, A2, cixi * B2);
+        PI.a = fmaf_(ce, A2, T(M.ci2bI) * xi * B);
+        PI.b = fmaf_(T(M.ce2bE) * xe, A, ci * B2);
+        PI.q = fmaf_(C.ei, fmaf_(T(M.ce2bE), A, T(M.ci2bI) * B), g.pq0);
+        // S2 = Pi phi(G)
+        S2.v = PI.v * g.phi;
+        S2.a = fmaf_(PI.a, g.phi, PI.v * g.phi1aE);
+        S2.b = fmaf_(PI.b, g.phi, PI.v * g.phi1aI);
+        S2.q = fmaf_(PI.q, g.phi, fmaf_(PI.v, g.phi2qG, fmaf_(PI.a, g.phi1nx, PI.b * g.phi1ny)));
         ITV = g.ITV;
         TV = g.TV;
     } else {
         // A_e = c_e xe A^2 / G^4 and A_i = c_i xi B^2 / G^4 weighted separately
-        Jet<T> Ae, Ai;
+        QJet<T> Ae, Ai;
         Ae.v = cexe * A2; Ae.a = ce * A2; Ae.b = T(M.ce2bE) * xe * A;
-        Ae.aa = T(0); Ae.ab = T(M.ce2bE) * A; Ae.bb = T(M.ce2bE2) * xe;
+        Ae.q = fmaf_(C.ei * T(M.ce2bE), A, T(0.5f) * C.ii * T(M.ce2bE2) * xe);
         Ai.v = cixi * B2; Ai.a = T(M.ci2bI) * xi * B; Ai.b = ci * B2;
-        Ai.aa = T(M.ci2bI2) * xi; Ai.ab = T(M.ci2bI) * B; Ai.bb = T(0);
+        Ai.q = fmaf_(C.ei * T(M.ci2bI), B, T(0.5f) * C.ee * T(M.ci2bI2) * xi);
         T r4 = r2 * r2;
-        Jet<T> R4 = jofG(r4, T(-4) * r4 * r, T(20) * r4 * r2, aE, aI);
-        Ae = jmul(Ae, R4);
-        Ai = jmul(Ai, R4);
-        Jet<T> De = jofG(de, he1, he2, aE, aI);
+        QJet<T> R4 = qofG(r4, T(-4) * r4 * r, T(20) * r4 * r2, aE, aI, C);
+        Ae = qmul(Ae, R4, C);
+        Ai = qmul(Ai, R4, C);
+        QJet<T> De = qofG(g.de, g.he1, g.he2, aE, aI, C);
         T di = rcp(fmaf_(T(M.Cm), r, T(M.tau_i)));
         T qi = di * r;
         T hi1 = T(M.Cm) * qi * qi;
         const T hi2 = T(-2) * T(M.tau_i) * hi1 * qi;
-        Jet<T> Di = jofG(di, hi1, hi2, aE, aI);
-        S2 = jadd(jmul(Ae, De), jmul(Ai, Di));
+        QJet<T> Di = qofG(di, hi1, hi2, aE, aI, C);
+        S2 = qadd(qmul(Ae, De, C), qmul(Ai, Di, C));
         // 1/tau_V = (A_e d_e + A_i d_i)/(A_e + A_i) = d_e + w (d_i - d_e) with
         // w = A_i/(A_e + A_i): a weighted mean of d_e, d_i whose derivatives do
         // not cancel when one source dominates (the ratio form loses them in FP32).
-        Jet<T> As = jadd(Ae, Ai);
+        QJet<T> As = qadd(Ae, Ai);
         T ra = rcp(As.v);
         T ra2 = ra * ra;
-        Jet<T> RA = jchain(As, ra, -ra2, T(2) * ra2 * ra);
-        Jet<T> Wi = jmul(Ai, RA);
-        Jet<T> Dd = jofG(di - de, hi1 - he1, hi2 - he2, aE, aI);
-        ITV = jadd(De, jmul(Wi, Dd));
+        QJet<T> RA = qchain(As, ra, -ra2, T(2) * ra2 * ra, C);
+        QJet<T> Wi = qmul(Ai, RA, C);
+        QJet<T> Dd = qofG(di - g.de, hi1 - g.he1, hi2 - g.he2, aE, aI, C);
+        ITV = qadd(De, qmul(Wi, Dd, C));
         T itv = rcp(ITV.v);
         T itv2 = itv * itv;
-        TV = jchain(ITV, itv, -itv2, T(2) * itv2 * itv);
+        TV = qchain(ITV, itv, -itv2, T(2) * itv2 * itv, C);
     }
     // q = S2^(-1/2) = 1/(sqrt2 sigma_V);  (x^-1/2)' = -q^3/2, '' = 3 q^5/4
+    // SQ = sqrt(S2) = sqrt2 sigma_V;      (x^1/2)' = q/2,     '' = -q^3/4
+    T cs2x, cs2y;
+    cvec(C, S2.a, S2.b, cs2x, cs2y);                 // C grad S2
+    const T hq2 = T(0.5f) * fmaf_(S2.a, cs2x, S2.b * cs2y);
     T q = rsq(S2.v);
     T q2 = q * q, q3 = q2 * q;
-    Jet<T> Q = jchain(S2, q, T(-0.5f) * q3, T(0.75f) * q3 * q2);
-    // SQ = sqrt(S2) = sqrt2 sigma_V;  (x^1/2)' = q/2, '' = -q^3/4
-    Jet<T> SQ = jchain(S2, S2.v * q, T(0.5f) * q, T(-0.25f) * q3);
+    const T f1 = T(-0.5f) * q3, h1 = T(0.5f) * q;
+    QJet<T> Q{q, f1 * S2.a, f1 * S2.b, fmaf_(f1, S2.q, T(0.75f) * q3 * q2 * hq2)};
+    QJet<T> SQ{S2.v * q, h1 * S2.a, h1 * S2.b, fmaf_(h1, S2.q, T(-0.25f) * q3 * hq2)};
     // V = V_thre - mu_V with the threshold polynomial p of Table 1 written in
     // the offsets d = u - c of u = (mu_V, SQ, tau_V) from the centre c of its
     // normalisation: p = P0 + L.d + d.H d / 2 with L_k = P_k s_k and the constant
-    // Hessian H_kl = s_k s_l d2p/dn_k dn_l, so grad p = L + H d and the jet of
-    // V follows from the jets of u by the chain rule.
-    const float *L = M.plin[pop], *Hr = M.Hraw[pop];
+    // Hessian H_kl = s_k s_l d2p/dn_k dn_l, so grad p = L + H d, and
+    // q(V) = sum_k (dV/du_k) q(u_k) + sum_kl H_kl (grad u_k . C grad u_l) / 2.
+    const float *L = M.plin[pop], *Hr = M.Hraw[pop], *Hq = M.Hq[pop];
     T d0 = MU.v - T(M.pc[0]), d1 = SQ.v - T(M.pc[1]), d2 = TV.v - T(M.pc[2]);
     T k0 = fmaf_(T(Hr[0]), d0, fmaf_(T(Hr[1]), d1, fmaf_(T(Hr[2]), d2, T(L[0]))));
     T k1 = fmaf_(T(Hr[1]), d0, fmaf_(T(Hr[3]), d1, fmaf_(T(Hr[4]), d2, T(L[1]))));
     T k2 = fmaf_(T(Hr[2]), d0, fmaf_(T(Hr[4]), d1, fmaf_(T(Hr[5]), d2, T(L[2]))));
-    Jet<T> V;
+    QJet<T> V;
     V.v = fmaf_(T(0.5f), fmaf_(d0, T(L[0]) + k0, fmaf_(d1, T(L[1]) + k1, d2 * (T(L[2]) + k2))),
                 T(M.P0[pop]) - MU.v);
     const T u0 = k0 - T(1);
     V.a = fmaf_(u0, MU.a, fmaf_(k1, SQ.a, k2 * TV.a));
     V.b = fmaf_(u0, MU.b, fmaf_(k1, SQ.b, k2 * TV.b));
-    // H u_a and H u_b
-    T wa0 = fmaf_(T(Hr[0]), MU.a, fmaf_(T(Hr[1]), SQ.a, T(Hr[2]) * TV.a));
-    T wa1 = fmaf_(T(Hr[1]), MU.a, fmaf_(T(Hr[3]), SQ.a, T(Hr[4]) * TV.a));
-    T wa2 = fmaf_(T(Hr[2]), MU.a, fmaf_(T(Hr[4]), SQ.a, T(Hr[5]) * TV.a));
-    T wb0 = fmaf_(T(Hr[0]), MU.b, fmaf_(T(Hr[1]), SQ.b, T(Hr[2]) * TV.b));
-    T wb1 = fmaf_(T(Hr[1]), MU.b, fmaf_(T(Hr[3]), SQ.b, T(Hr[4]) * TV.b));
-    T wb2 = fmaf_(T(Hr[2]), MU.b, fmaf_(T(Hr[4]), SQ.b, T(Hr[5]) * TV.b));
-    V.aa = fmaf_(u0, MU.aa, fmaf_(k1, SQ.aa, fmaf_(k2, TV.aa,
-           fmaf_(wa0, MU.a, fmaf_(wa1, SQ.a, wa2 * TV.a)))));
-    V.ab = fmaf_(u0, MU.ab, fmaf_(k1, SQ.ab, fmaf_(k2, TV.ab,
-           fmaf_(wa0, MU.b, fmaf_(wa1, SQ.b, wa2 * TV.b)))));
-    V.bb = fmaf_(u0, MU.bb, fmaf_(k1, SQ.bb, fmaf_(k2, TV.bb,
-           fmaf_(wb0, MU.b, fmaf_(wb1, SQ.b, wb2 * TV.b)))));
-    Jet<T> Z = jmul(V, Q);                            // (V_thre - mu_V)/(sqrt2 sigma_V)
+    // M_kl = grad u_k . C grad u_l with C grad SQ = (q/2) C grad S2 and
+    // C grad tau_V = tau_V' C n in the tau_e == tau_i case
+    T cm0x, cm0y, ct2x, ct2y, m22;
+    cvec(C, MU.a, MU.b, cm0x, cm0y);
+    if constexpr (EQ) {
+        ct2x = g.tv1nx;
+        ct2y = g.tv1ny;
+        m22 = g.m22;
+    } else {
+        cvec(C, TV.a, TV.b, ct2x, ct2y);
+        m22 = fmaf_(TV.a, ct2x, TV.b * ct2y);
+    }
+    const T c1x = h1 * cs2x, c1y = h1 * cs2y;
+    const T m00 = fmaf_(MU.a, cm0x, MU.b * cm0y);
+    const T m01 = fmaf_(MU.a, c1x, MU.b * c1y);
+    const T m02 = fmaf_(MU.a, ct2x, MU.b * ct2y);
+    const T m11 = h1 * h1 * T(2) * hq2;
+    const T m12 = fmaf_(SQ.a, ct2x, SQ.b * ct2y);
+    V.q = fmaf_(u0, MU.q, fmaf_(k1, SQ.q, fmaf_(k2, TV.q,
+          fmaf_(T(Hq[0]), m00, fmaf_(T(Hq[3]), m11, fmaf_(T(Hq[5]), m22,
+          fmaf_(T(Hq[1]), m01, fmaf_(T(Hq[2]), m02, T(Hq[4]) * m12))))))));
+    // Z = V q: (V_thre - mu_V)/(sqrt2 sigma_V); C grad q = f1 C grad S2
+    QJet<T> Z;
+    Z.v = V.v * Q.v;
+    Z.a = fmaf_(V.a, Q.v, V.v * Q.a);
+    Z.b = fmaf_(V.b, Q.v, V.v * Q.b);
+    Z.q = fmaf_(V.q, Q.v, fmaf_(V.v, Q.q, f1 * fmaf_(V.a, cs2x, V.b * cs2y)));
     T ez, e;
     erfc_and_gauss(Z.v, ez, e);
     // F = erfc(Z) / (2 tau_V): the factor 1/2 rides on erfc's chain coefficients
     T g1 = T(-0.5f * 1.1283791670955126f) * e;
-    Jet<T> GZ = jchain(Z, T(0.5f) * ez, g1, T(-2) * Z.v * g1);
-    return jmul(GZ, ITV);
+    QJet<T> GZ = qchain(Z, T(0.5f) * ez, g1, T(-2) * Z.v * g1, C);
+    if constexpr (EQ) {
+        // F = GZ (1/tau_V) with 1/tau_V = d_e(G)
+        QJet<T> F;
+        F.v = GZ.v * ITV.v;
+        F.a = fmaf_(GZ.a, ITV.v, GZ.v * ITV.a);
+        F.b = fmaf_(GZ.b, ITV.v, GZ.v * ITV.b);
+        F.q = fmaf_(GZ.q, ITV.v, fmaf_(GZ.v, g.itv2qG, fmaf_(GZ.a, g.itv1nx, GZ.b * g.itv1ny)));
+        return F;
+    } else {
+        return qmul(GZ, ITV, C);
+    }
 }
 
 // Per-instance parameters.
@@ -389,24 +415,31 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
     T xi0 = maxf_(I + T(M.cF[0][1]), T(M.x_floor));
     T xe1 = maxf_(exc + T(M.cF[1][0]), T(M.x_floor));
     T xi1 = maxf_(I + T(M.cF[1][1]), T(M.x_floor));
+    // the covariance of the inputs (xe, xi) is that of the rates (E, I)
+    Cov<T> C;
+    C.ee = Cee;
+    C.ei = Cei;
+    C.ii = Cii;
+    cvec(C, T(M.aE), T(M.aI), C.nx, C.ny);
+    C.qG = T(0.5f) * fmaf_(T(M.aE), C.nx, T(M.aI) * C.ny);
     T muVe, muVi;
     constexpr bool EQ = (VAR & kVarEq) != 0;
-    const TFShared<T> g0 = tf_shared<EQ>(M, xe0, xi0);
-    Jet<T> Fe = transfer<EQ>(M, 0, g0, X[5], muVe);
-    Jet<T> Fi;
+    const TFShared<T> g0 = tf_shared<EQ>(M, xe0, xi0, C);
+    QJet<T> Fe = transfer<EQ>(M, 0, g0, C, X[5], muVe);
+    QJet<T> Fi;
     if constexpr ((VAR & kVarSame) != 0) {
         (void)xe1;
         (void)xi1;
-        Fi = transfer<EQ>(M, 1, g0, X[6], muVi);
+        Fi = transfer<EQ>(M, 1, g0, C, X[6], muVi);
     } else {
-        const TFShared<T> g1 = tf_shared<EQ>(M, xe1, xi1);
-        Fi = transfer<EQ>(M, 1, g1, X[6], muVi);
+        const TFShared<T> g1 = tf_shared<EQ>(M, xe1, xi1, C);
+        Fi = transfer<EQ>(M, 1, g1, C, X[6], muVi);
     }
     const T iT = T(M.invT);
     T fe = Fe.v - E, fi = Fi.v - I;
-    // eq. 1: T dnu/dt = (F - nu) + 1/2 C_ee F_ee + C_ei F_ei + 1/2 C_ii F_ii
-    dX[0] = iT * fmaf_(T(0.5f), fmaf_(Cee, Fe.aa, Cii * Fe.bb), fmaf_(Cei, Fe.ab, fe));
-    dX[1] = iT * fmaf_(T(0.5f), fmaf_(Cee, Fi.aa, Cii * Fi.bb), fmaf_(Cei, Fi.ab, fi));
+    // eq. 1: T dnu/dt = (F - nu) + 1/2 C_ee F_ee + C_ei F_ei + 1/2 C_ii F_ii = (F - nu) + q(F)
+    dX[0] = iT * (Fe.q + fe);
+    dX[1] = iT * (Fi.q + fi);
     // eq. 2
     dX[2] = iT * fmaf_(Fe.v * (iT - Fe.v), T(M.invNe),
                        fmaf_(fe, fe, T(2) * (fmaf_(Cee, Fe.a, Cei * Fe.b) - Cee)));

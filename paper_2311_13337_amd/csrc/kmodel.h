@@ -48,7 +48,11 @@ inline KModel make_kmodel(const vadx_model &m)
         for (int i = 0; i < 3; ++i) k.plin[p][i] = (float)(P[1 + i] * sc[i]);
         int q = 0;
         for (int i = 0; i < 3; ++i)
-            for (int j = i; j < 3; ++j) k.Hraw[p][q++] = (float)(sc[i] * sc[j] * H[i][j]);
+            for (int j = i; j < 3; ++j) {
+                k.Hraw[p][q] = (float)(sc[i] * sc[j] * H[i][j]);
+                k.Hq[p][q] = (float)((i == j ? 0.5 : 1.0) * sc[i] * sc[j] * H[i][j]);
+                ++q;
+            }
     }
     k.invT = (float)(1.0 / m.T); k.invNe = (float)(1.0 / m.N_e); k.invNi = (float)(1.0 / m.N_i);
     k.inv_tauw[0] = (float)(1.0 / m.tau_w_e); k.inv_tauw[1] = (float)(1.0 / m.tau_w_i);

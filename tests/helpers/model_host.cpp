@@ -9,16 +9,30 @@ using namespace vadx;
 
 extern "C" {
 
+// Value, gradient, Hessian (from q with C = 2 e_e e_e^T, 2 e_i e_i^T and
+// e_e e_i^T + e_i e_e^T) and mu_V of one population's transfer function.
 void mh_tf(const vadx_model *m, int pop, float xe, float xi, float W, float *out)
 {
     KModel k = make_kmodel(*m);
     float mu = 0.f;
-    Jet<float> F;
-    if (m->tau_e == m->tau_i)
-        F = transfer<true>(k, pop, tf_shared<true>(k, xe, xi), W, mu);
-    else
-        F = transfer<false>(k, pop, tf_shared<false>(k, xe, xi), W, mu);
-    out[0] = F.v; out[1] = F.a; out[2] = F.b; out[3] = F.aa; out[4] = F.ab; out[5] = F.bb; out[6] = mu;
+    const float cs[3][3] = {{2.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 2.f}};
+    float hq[3];
+    QJet<float> F{};
+    for (int t = 0; t < 3; ++t) {
+        Cov<float> C;
+        C.ee = cs[t][0];
+        C.ei = cs[t][1];
+        C.ii = cs[t][2];
+        cvec(C, k.aE, k.aI, C.nx, C.ny);
+        C.qG = 0.5f * (k.aE * C.nx + k.aI * C.ny);
+        if (m->tau_e == m->tau_i)
+            F = transfer<true>(k, pop, tf_shared<true>(k, xe, xi, C), C, W, mu);
+        else
+            F = transfer<false>(k, pop, tf_shared<false>(k, xe, xi, C), C, W, mu);
+        hq[t] = F.q;
+    }
+    out[0] = F.v; out[1] = F.a; out[2] = F.b; out[3] = hq[0]; out[4] = hq[1]; out[5] = hq[2];
+    out[6] = mu;
 }
 
 void mh_drift(const vadx_model *m, const float *X, float c, float be, float ae, float *dX)
