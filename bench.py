@@ -39,6 +39,10 @@ def parse():
                    help="register budget of the integration kernel when not autotuning")
     p.add_argument("--wg-instances", type=int, default=0,
                    help="instances per workgroup when not autotuning (0 = as many as fit 512 lanes)")
+    p.add_argument("--item-steps", type=int, default=0,
+                   help="queue item length with --no-autotune (0 = 1000)")
+    p.add_argument("--tune-steps", type=int, default=16000,
+                   help="steps of each autotuner trial run")
     p.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "vadx_tune.json"))
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-instances", type=int, default=64)
@@ -137,12 +141,13 @@ def main():
     run = vadx.make_run(cfg)
     sw.plan(run)
     sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
-    sw.ctx.vadx_set_launch(0, args.wg_instances, 0)
+    sw.ctx.vadx_set_launch(0, args.wg_instances, args.item_steps)
     sw.plan(run)
-    shape = {"instances_per_workgroup": args.wg_instances or "max", "item_steps": 1000,
+    shape = {"instances_per_workgroup": args.wg_instances or "max",
+             "item_steps": args.item_steps or 1000,
              "waves_per_simd": args.waves_per_simd, "autotuned": False}
     if not args.no_autotune:
-        lanes, items, waves = sw.autotune(args.tune_cache, trial_steps=5000)
+        lanes, items, waves = sw.autotune(args.tune_cache, trial_steps=args.tune_steps)
         shape = {"lanes_per_workgroup": lanes, "item_steps": items, "waves_per_simd": waves,
                  "autotuned": True}
     ctx = sw.ctx

@@ -203,7 +203,8 @@ vadx_status vadx_set_waves_per_simd(vadx_ctx *ctx, int32_t waves);
  * the size vadx_plan gave for `run`; its contents are overwritten) for
  * workgroup lane budgets of 64..512 lanes -- each region-count class then
  * packs floor(budget / n) instances per workgroup -- times 2 or 3 waves per
- * SIMD, then queue items of 250, 1000 and 4000 steps, and keeps the fastest
+ * SIMD with 1000-step queue items, then, at the fastest lane budget, 2 or 3
+ * waves per SIMD with items of 500..8000 steps, and keeps the fastest
  * (persistent launch). With a cache_path (nullable) the choice is read from /
  * added to that JSON file, keyed by device, block length and the
  * region-count mix; a cached choice is applied without trials. *lanes,

@@ -473,8 +473,15 @@ template <class S> VADX_HD bool project(const KModel &M, S X[8])
     X[1] = clampv(X[1], S(0), rm, hit);
     X[2] = clampv(X[2], S(0), X[0] * (rm - X[0]), hit);
     X[4] = clampv(X[4], S(0), X[1] * (rm - X[1]), hit);
-    S cb = sqr(X[2] * X[4]);
-    X[3] = clampv(X[3], -cb, cb, hit);
+    // |C_ei| <= sqrt(C_ee C_ii): the square root is taken only where the bound
+    // may bind. Below C_ei^2 < C_ee C_ii (1 - 2^-40) (each side rounded),
+    // |C_ei| < sqrt(C_ee C_ii) in any rounding, so the clamp would leave C_ei
+    // unchanged and flag nothing.
+    const S p = X[2] * X[4];
+    if (X[3] * X[3] >= p * S(0.99999999999909051)) {
+        S cb = sqr(p);
+        X[3] = clampv(X[3], -cb, cb, hit);
+    }
     return hit;
 }
 

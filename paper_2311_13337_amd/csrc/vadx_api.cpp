@@ -1055,11 +1055,14 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
                 }
             }
         }
-        for (int it : {250, 4000}) {
-            if (result) break;
-            result = trial(best_l, it, best_w, &ms);
-            if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; }
-        }
+        // the register budget and the item length together, at the chosen lane budget
+        for (int w : {2, 3})
+            for (int it : {500, 1000, 2000, 4000, 8000}) {
+                if (result) break;
+                if (w == best_w && it == 1000) continue;
+                result = trial(best_l, it, w, &ms);
+                if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; best_w = w; }
+            }
         if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_w, best_ms);
     }
     restore();
