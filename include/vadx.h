@@ -97,7 +97,9 @@ typedef struct vadx_run {
 /* Summary statistics of one instance (definitions in vadx_read_stats). */
 typedef struct vadx_stats {
     float fc_mean, fc_std, fc_sc_corr, rate_mean_hz, rate_std_hz, sync_index;
-    uint32_t flags, reserved;
+    uint32_t flags;
+    float fc_fit;         /* Pearson correlation of FC_kl with the connectome's reference FC
+                             over k < l (vadx_set_reference_fc); 0 without a reference */
 } vadx_stats;
 
 /* Creates a context on HIP device `device` enqueuing on `hip_stream`
@@ -177,6 +179,21 @@ vadx_status vadx_read_fc(vadx_ctx *ctx, int64_t inst, float *out, int32_t where)
 vadx_status vadx_read_samples(vadx_ctx *ctx, int64_t inst, float *out, int32_t where);
 vadx_status vadx_read_state(vadx_ctx *ctx, int64_t inst, double *out, int32_t where);
 vadx_status vadx_read_trace(vadx_ctx *ctx, int64_t slot, float *out, int32_t where);
+
+/* Reference FC of connectome conn_id (Section 2.4, "-ff"): host array fc
+ * [n*n] (row-major, copied; finite), or NULL to remove it. Each instance on
+ * that connectome then reports vadx_stats.fc_fit, the Pearson correlation of
+ * its FC with the reference over the pairs k < l (0 when either has no
+ * variance) -- the fitness a grid search ranks (vadx_top_k). */
+vadx_status vadx_set_reference_fc(vadx_ctx *ctx, int32_t conn_id, const float *fc);
+
+/* Ranking of a sweep (the grid search's sort of fitness, Section 2.5, "-gs"):
+ * of n device scores (FP32, not NaN), the k largest in decreasing order, ties
+ * by increasing index. idx (device, k entries) receives the indices, val
+ * (device, nullable) the scores. 0 <= k <= min(n, 1024). Synchronises the
+ * context's stream. */
+vadx_status vadx_top_k(vadx_ctx *ctx, const float *score, int64_t n, int32_t k, int64_t *idx,
+                       float *val);
 
 /* Region count and number of post-transient samples of instance `inst` for
  * the last plan (sizes of the read_* outputs). */

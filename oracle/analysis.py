@@ -155,6 +155,31 @@ def mean_upper(M: np.ndarray) -> float:
     return float(M[iu].mean())
 
 
+def fc_fitness(fc: np.ndarray, ref: np.ndarray) -> float:
+    """Fitness of a simulated FC against a reference FC (Section 2.4, the
+    comparison with an externally obtained FC): the Pearson correlation of
+    FC_kl and ref_kl over the pairs k < l; 0 when either has no variance."""
+    n = fc.shape[0]
+    iu = np.triu_indices(n, 1)
+    a = np.asarray(fc, np.float64)[iu]
+    b = np.asarray(ref, np.float64)[iu]
+    if a.size == 0:
+        return 0.0
+    da, db = a - a.mean(), b - b.mean()
+    va, vb = np.sum(da * da), np.sum(db * db)
+    if not (va > 0 and vb > 0):
+        return 0.0
+    return float(np.sum(da * db) / np.sqrt(va * vb))
+
+
+def top_k(score: np.ndarray, k: int) -> np.ndarray:
+    """Indices of the k largest scores in decreasing order, ties by increasing
+    index (the grid search's ranking)."""
+    s = np.asarray(score, np.float64)
+    order = np.lexsort((np.arange(len(s)), -s))
+    return order[:k]
+
+
 def ud_thresholds(x_khz: np.ndarray, band: float, min_range: float):
     """Single-precision thresholds (up, down) of one region, or None."""
     x = np.asarray(x_khz, np.float32)

@@ -36,6 +36,7 @@ struct ConnDev {
     int64_t row_off;    // into rowptr (n + 1 entries)
     int64_t edge_off;   // into colw / len arrays (nnz entries)
     int64_t sc_off;     // into raw weights (n*n doubles)
+    int64_t ref_off;    // into reference FC matrices (n*n floats); -1: none
 };
 
 // A workgroup's share: `count` instances of the same region count.
@@ -86,8 +87,9 @@ struct FcArgs {
     const InstDev *inst;
     const ConnDev *conns;
     const double *sc;           // raw weights, [n][n] per connectome
+    const float *ref;           // reference FC matrices, [n][n] per connectome that has one
     float *ws;
-    float *stats;               // [inst][8] as vadx_stats (6 floats + flags + reserved)
+    float *stats;               // [inst][8] as vadx_stats (6 floats + flags + fc_fit)
     uint32_t *flags;
     int64_t n_samples;
     double min_var;             // silence threshold on a region's variance
@@ -106,6 +108,8 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
                             const QueueArgs *q, int grid, int occ, hipStream_t s);
 int persistent_blocks_per_cu(int block, int block_threads, int occ);
+hipError_t launch_rank_sort(const float *val, const int64_t *idx, int32_t k, int64_t *idx_out,
+                            float *val_out, hipStream_t s);
 hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s);
 
 } // namespace vadx

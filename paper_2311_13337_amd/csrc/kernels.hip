@@ -472,6 +472,7 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
     const int64_t ns = a.n_samples;
     const float *x = a.ws + I.samp_off;
     const double *sc = a.sc + C.sc_off;
+    const float *ref = C.ref_off >= 0 ? a.ref + C.ref_off : nullptr;
     float *fc = a.ws + I.fc_off;
     const double inv_ns = ns > 0 ? 1.0 / (double)ns : 0.0;
 
@@ -483,6 +484,7 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
     const int ntiles = nT * (nT + 1) / 2;
     const int chunk = kFcLdsFloats / npad;
     double s_f = 0, s_f2 = 0, s_w = 0, s_w2 = 0, s_fw = 0, s_cov = 0;
+    double s_r = 0, s_r2 = 0, s_fr = 0;           // reference FC (fitness)
     // per-region sums of the shifted samples and of their squares, gathered
     // from the LDS-staged samples during the first pass over the tiles
     double m1[kFcRegionsPerThread], m2[kFcRegionsPerThread];
@@ -585,6 +587,12 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
                     s_w2 = fma(wv, wv, s_w2);
                     s_fw = fma(f, wv, s_fw);
                     s_cov += 2.0 * cov;
+                    if (ref) {
+                        const double rv = (double)ref[(int64_t)k * n + l];
+                        s_r += rv;
+                        s_r2 = fma(rv, rv, s_r2);
+                        s_fr = fma(f, rv, s_fr);
+                    }
                 }
         }
     }
@@ -605,6 +613,11 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
     s_mean = block_sum(s_mean, red);
     s_std = block_sum(s_std, red);
     s_var = block_sum(s_var, red);
+    if (ref) {
+        s_r = block_sum(s_r, red);
+        s_r2 = block_sum(s_r2, red);
+        s_fr = block_sum(s_fr, red);
+    }
     const double zv = block_sum((double)zero_var, red);
     if (tid == 0) {
         const double cnt = 0.5 * (double)n * (double)(n - 1);
@@ -620,8 +633,44 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
         st[5] = (float)(s_var > 0.0 ? sqrt((s_cov / ((double)n * n)) / (s_var / n)) : 0.0);
         uint32_t flags = a.flags[inst] | (zv > 0.0 ? 4u : 0u);
         ((uint32_t *)st)[6] = flags;
-        ((uint32_t *)st)[7] = 0u;
+        // fitness: Pearson correlation of FC_kl with the reference over k < l
+        const double vr = s_r2 - s_r * s_r / cnt, cfr = s_fr - s_f * s_r / cnt;
+        st[7] = (float)((ref && vf > 0.0 && vr > 0.0) ? cfr / sqrt(vf * vr) : 0.0);
     }
+}
+
+// Orders k (value, index) pairs by decreasing value, ties by increasing index:
+// each pair's output position is the number of pairs that precede it.
+constexpr int kRankMax = 1024;
+__global__ __launch_bounds__(kRankMax) void rank_sort_kernel(const float *val, const int64_t *idx,
+                                                             int32_t k, int64_t *idx_out,
+                                                             float *val_out)
+{
+    __shared__ float v[kRankMax];
+    __shared__ int64_t ix[kRankMax];
+    const int t = threadIdx.x;
+    if (t < k) {
+        v[t] = val[idx[t]];
+        ix[t] = idx[t];
+    }
+    __syncthreads();
+    if (t < k) {
+        int r = 0;
+        for (int j = 0; j < k; ++j)
+            r += (v[j] > v[t] || (v[j] == v[t] && ix[j] < ix[t])) ? 1 : 0;
+        idx_out[r] = ix[t];
+        if (val_out) val_out[r] = v[t];
+    }
+}
+
+hipError_t launch_rank_sort(const float *val, const int64_t *idx, int32_t k, int64_t *idx_out,
+                            float *val_out, hipStream_t s)
+{
+    if (k <= 0) return hipSuccess;
+    if (k > kRankMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rank_sort_kernel, dim3(1), dim3(kRankMax), 0, s, val, idx, k, idx_out,
+                       val_out);
+    return hipGetLastError();
 }
 
 hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s)

@@ -28,8 +28,7 @@ struct vadx_mlp {
     double *stat = nullptr;          // target statistics scratch (12 doubles)
     float *loss1 = nullptr;          // loss sum of one gradient evaluation
     // selection scratch: 256 histogram bins, then per-tile counts and bases
-    void *sel_scratch = nullptr;
-    int64_t sel_tiles = -1;
+    vadx::SelScratch sel;
 };
 
 static vadx_status mfail(vadx_mlp *m, vadx_status st, const char *msg, hipError_t e = hipSuccess)
@@ -85,6 +84,107 @@ __global__ void mlp_target_stats_kernel(const float *Y, int64_t n, double *out)
         out[6 + c] = var > 0.0 ? std::sqrt(var) : 1.0;
     }
 }
+
+namespace vadx {
+
+#define SHIP(expr)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);                   \
+            return e_ == hipErrorOutOfMemory ? VADX_E_OOM : VADX_E_HIP;                \
+        }                                                                              \
+    } while (0)
+
+vadx_status select_run(hipStream_t s, SelScratch &sc, const float *score, int64_t n, int64_t k,
+                       float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
+                       int64_t capacity, int64_t *n_sel, std::string &err)
+{
+    if (!n_sel || n < 0 || k < 0 || (n > 0 && !score) || capacity < 0 ||
+        (capacity > 0 && !sel) || !(audit_frac >= 0.f && audit_frac <= 1.f)) {
+        err = "bad arguments";
+        return VADX_E_ARG;
+    }
+    if (n > ((int64_t)1 << 40)) { err = "too many points"; return VADX_E_UNSUPPORTED; }
+    *n_sel = 0;
+    if (n == 0) return VADX_OK;
+    if (k > n) k = n;
+    const int64_t tiles = select_tiles(n);
+    // scratch layout: hist u32[256] | counts u32[tiles] | eq_base i64[tiles] | sel_base i64[tiles]
+    const size_t off_cnt = 256 * sizeof(uint32_t);
+    const size_t off_eq = (off_cnt + tiles * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t off_sb = off_eq + tiles * sizeof(int64_t);
+    const size_t bytes = off_sb + tiles * sizeof(int64_t);
+    if (tiles > sc.tiles) {
+        if (sc.p) (void)hipFree(sc.p);
+        sc.p = nullptr;
+        sc.tiles = -1;
+        SHIP(hipMalloc(&sc.p, bytes));
+        sc.tiles = tiles;
+    }
+    char *base = (char *)sc.p;
+    uint32_t *hist = (uint32_t *)base;
+    uint32_t *counts = (uint32_t *)(base + off_cnt);
+    int64_t *eq_base = (int64_t *)(base + off_eq);
+    int64_t *sel_base = (int64_t *)(base + off_sb);
+
+    // radix select of the k-th largest key: T and the number of keys equal to
+    // T that belong to the top k
+    uint32_t prefix = 0, mask = 0;
+    int64_t need = k;
+    const int use_top = k > 0;
+    if (use_top) {
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            uint32_t h[256];
+            SHIP(hipMemsetAsync(hist, 0, 256 * sizeof(uint32_t), s));
+            SHIP(launch_sel_hist(score, n, prefix, mask, shift, hist, s));
+            SHIP(hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s));
+            SHIP(hipStreamSynchronize(s));
+            int b = 255;
+            for (; b > 0; --b) {
+                if ((int64_t)h[b] >= need) break;
+                need -= h[b];
+            }
+            prefix |= (uint32_t)b << shift;
+            mask |= 0xFFu << shift;
+        }
+    }
+    std::vector<uint32_t> hc((size_t)tiles);
+    std::vector<int64_t> hb((size_t)tiles);
+    // phase 0: keys equal to T per tile -> eq_base
+    if (use_top) {
+        SHIP(launch_sel_compact(score, n, 0, 1, prefix, need, 0.f, seed, nullptr, nullptr,
+                                counts, nullptr, nullptr, s));
+        SHIP(hipMemcpyAsync(hc.data(), counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SHIP(hipStreamSynchronize(s));
+    }
+    int64_t acc = 0;
+    for (int64_t t = 0; t < tiles; ++t) {
+        hb[(size_t)t] = acc;
+        acc += use_top ? hc[(size_t)t] : 0;
+    }
+    SHIP(hipMemcpyAsync(eq_base, hb.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // phase 1: selected points per tile -> sel_base
+    SHIP(launch_sel_compact(score, n, 1, use_top, prefix, need, audit_frac, seed, eq_base,
+                            nullptr, counts, nullptr, nullptr, s));
+    SHIP(hipMemcpyAsync(hc.data(), counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SHIP(hipStreamSynchronize(s));
+    acc = 0;
+    for (int64_t t = 0; t < tiles; ++t) {
+        hb[(size_t)t] = acc;
+        acc += hc[(size_t)t];
+    }
+    *n_sel = acc;
+    if (acc > capacity) { err = "selection larger than the output capacity"; return VADX_E_OOM; }
+    SHIP(hipMemcpyAsync(sel_base, hb.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // phase 2: write the indices
+    SHIP(launch_sel_compact(score, n, 2, use_top, prefix, need, audit_frac, seed, eq_base,
+                            sel_base, nullptr, sel, is_audit, s));
+    SHIP(hipStreamSynchronize(s));
+    return VADX_OK;
+}
+
+} // namespace vadx
 
 extern "C" {
 
@@ -153,7 +253,7 @@ void vadx_mlp_destroy(vadx_mlp *m)
     if (m->losses) (void)hipFree(m->losses);
     if (m->stat) (void)hipFree(m->stat);
     if (m->loss1) (void)hipFree(m->loss1);
-    if (m->sel_scratch) (void)hipFree(m->sel_scratch);
+    if (m->sel.p) (void)hipFree(m->sel.p);
     delete m;
 }
 
@@ -290,86 +390,11 @@ vadx_status vadx_mlp_select(vadx_mlp *m, const float *score, int64_t n, int64_t 
                             float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
                             int64_t capacity, int64_t *n_sel)
 {
-    if (!m || !n_sel || n < 0 || k < 0 || (n > 0 && !score) || capacity < 0 ||
-        (capacity > 0 && !sel) || !(audit_frac >= 0.f && audit_frac <= 1.f))
-        return mfail(m, VADX_E_ARG, "bad arguments");
-    if (n > ((int64_t)1 << 40)) return mfail(m, VADX_E_UNSUPPORTED, "too many points");
-    *n_sel = 0;
-    if (n == 0) return VADX_OK;
-    if (k > n) k = n;
-    const int64_t tiles = select_tiles(n);
-    // scratch layout: hist u32[256] | counts u32[tiles] | eq_base i64[tiles] | sel_base i64[tiles]
-    const size_t off_cnt = 256 * sizeof(uint32_t);
-    const size_t off_eq = (off_cnt + tiles * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t off_sb = off_eq + tiles * sizeof(int64_t);
-    const size_t bytes = off_sb + tiles * sizeof(int64_t);
-    if (tiles > m->sel_tiles) {
-        if (m->sel_scratch) (void)hipFree(m->sel_scratch);
-        m->sel_scratch = nullptr;
-        m->sel_tiles = -1;
-        MHIP(m, hipMalloc(&m->sel_scratch, bytes));
-        m->sel_tiles = tiles;
-    }
-    char *base = (char *)m->sel_scratch;
-    uint32_t *hist = (uint32_t *)base;
-    uint32_t *counts = (uint32_t *)(base + off_cnt);
-    int64_t *eq_base = (int64_t *)(base + off_eq);
-    int64_t *sel_base = (int64_t *)(base + off_sb);
-    hipStream_t s = m->stream;
-
-    // radix select of the k-th largest key: T and the number of keys equal to
-    // T that belong to the top k
-    uint32_t prefix = 0, mask = 0;
-    int64_t need = k;
-    const int use_top = k > 0;
-    if (use_top) {
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            uint32_t h[256];
-            MHIP(m, hipMemsetAsync(hist, 0, 256 * sizeof(uint32_t), s));
-            MHIP(m, launch_sel_hist(score, n, prefix, mask, shift, hist, s));
-            MHIP(m, hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s));
-            MHIP(m, hipStreamSynchronize(s));
-            int b = 255;
-            for (; b > 0; --b) {
-                if ((int64_t)h[b] >= need) break;
-                need -= h[b];
-            }
-            prefix |= (uint32_t)b << shift;
-            mask |= 0xFFu << shift;
-        }
-    }
-    std::vector<uint32_t> hc((size_t)tiles);
-    std::vector<int64_t> hb((size_t)tiles);
-    // phase 0: keys equal to T per tile -> eq_base
-    if (use_top) {
-        MHIP(m, launch_sel_compact(score, n, 0, 1, prefix, need, 0.f, seed, nullptr, nullptr,
-                                   counts, nullptr, nullptr, s));
-        MHIP(m, hipMemcpyAsync(hc.data(), counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        MHIP(m, hipStreamSynchronize(s));
-    }
-    int64_t acc = 0;
-    for (int64_t t = 0; t < tiles; ++t) {
-        hb[(size_t)t] = acc;
-        acc += use_top ? hc[(size_t)t] : 0;
-    }
-    MHIP(m, hipMemcpyAsync(eq_base, hb.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    // phase 1: selected points per tile -> sel_base
-    MHIP(m, launch_sel_compact(score, n, 1, use_top, prefix, need, audit_frac, seed, eq_base,
-                               nullptr, counts, nullptr, nullptr, s));
-    MHIP(m, hipMemcpyAsync(hc.data(), counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    MHIP(m, hipStreamSynchronize(s));
-    acc = 0;
-    for (int64_t t = 0; t < tiles; ++t) {
-        hb[(size_t)t] = acc;
-        acc += hc[(size_t)t];
-    }
-    *n_sel = acc;
-    if (acc > capacity) return mfail(m, VADX_E_OOM, "selection larger than the output capacity");
-    MHIP(m, hipMemcpyAsync(sel_base, hb.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    // phase 2: write the indices
-    MHIP(m, launch_sel_compact(score, n, 2, use_top, prefix, need, audit_frac, seed, eq_base,
-                               sel_base, nullptr, sel, is_audit, s));
-    MHIP(m, hipStreamSynchronize(s));
+    if (!m) return VADX_E_ARG;
+    std::string err;
+    vadx_status st = select_run(m->stream, m->sel, score, n, k, audit_frac, seed, sel, is_audit,
+                                capacity, n_sel, err);
+    if (st) return mfail(m, st, err.c_str());
     return VADX_OK;
 }
 

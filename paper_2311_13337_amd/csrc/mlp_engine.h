@@ -3,6 +3,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string>
+
+#include "vadx.h"
 
 namespace vadx {
 
@@ -35,5 +38,17 @@ hipError_t launch_sel_compact(const float *score, int64_t n, int phase, int use_
                               int64_t need, float audit_frac, uint32_t seed, const int64_t *eq_base,
                               const int64_t *sel_base, uint32_t *out, int64_t *sel,
                               uint8_t *is_audit, hipStream_t s);
+
+// Device scratch of the selection (grown on demand, owned by the caller).
+struct SelScratch {
+    void *p = nullptr;
+    int64_t tiles = -1;
+};
+// The k largest scores (ties to the lower index) plus an audit sample of the
+// rest (probability audit_frac, Philox keyed (seed, index)), indices ascending;
+// synchronises s.
+vadx_status select_run(hipStream_t s, SelScratch &sc, const float *score, int64_t n, int64_t k,
+                       float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
+                       int64_t capacity, int64_t *n_sel, std::string &err);
 
 } // namespace vadx

@@ -19,6 +19,7 @@
 #include "analysis_engine.h"
 #include "engine.h"
 #include "kmodel.h"
+#include "mlp_engine.h"
 #include "vadx.h"
 
 using namespace vadx;
@@ -37,6 +38,8 @@ struct HostConn {
     int32_t n = 0, nnz = 0;
     double len_min = 0.0, len_max = 0.0;   // over edges with w != 0
     int64_t row_off = 0, edge_off = 0, sc_off = 0;
+    int64_t ref_off = -1;                  // reference FC slot (floats), -1: none
+    int64_t ref_slot = -1;                 // slot reserved at the first reference
 };
 
 template <class T> struct DevBuf {
@@ -78,6 +81,11 @@ struct vadx_ctx {
     DevBuf<float> weight;
     DevBuf<double> edge_len, sc;
     DevBuf<ConnDev> d_conns;
+    DevBuf<float> refs;                  // reference FC matrices (fitness)
+    int64_t total_ref = 0;
+    // ranking (vadx_top_k)
+    SelScratch sel;
+    DevBuf<int64_t> topk_idx;
     // batch
     std::vector<float> S, be, ae, v;
     std::vector<int32_t> conn_of;
@@ -253,6 +261,19 @@ vadx_status vadx_set_model(vadx_ctx *c, const vadx_model *m)
     return VADX_OK;
 }
 
+// Device copy of the connectome table (after a connectome or a reference changes).
+static vadx_status upload_conns(vadx_ctx *c)
+{
+    std::vector<ConnDev> dc;
+    for (auto &h : c->conns)
+        dc.push_back(ConnDev{h.n, h.nnz, h.row_off, h.edge_off, h.sc_off, h.ref_off});
+    HIP_TRY(c, c->d_conns.ensure(dc.size()));
+    HIP_TRY(c, hipMemcpyAsync(c->d_conns.p, dc.data(), dc.size() * sizeof(ConnDev),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return VADX_OK;
+}
+
 vadx_status vadx_add_connectome(vadx_ctx *c, int32_t n, const double *w, const double *len,
                                 int32_t *conn_id)
 {
@@ -324,12 +345,8 @@ vadx_status vadx_add_connectome(vadx_ctx *c, int32_t n, const double *w, const d
     c->total_edges += nnz;
     c->total_sc += (int64_t)n * n;
     c->conns.push_back(hc);
-    std::vector<ConnDev> dc;
-    for (auto &h : c->conns) dc.push_back(ConnDev{h.n, h.nnz, h.row_off, h.edge_off, h.sc_off});
-    HIP_TRY(c, c->d_conns.ensure(dc.size()));
-    HIP_TRY(c, hipMemcpyAsync(c->d_conns.p, dc.data(), dc.size() * sizeof(ConnDev),
-                              hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    vadx_status st = upload_conns(c);
+    if (st) return st;
     *conn_id = (int32_t)c->conns.size() - 1;
     c->planned = false;
     return VADX_OK;
@@ -640,6 +657,7 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     f.inst = c->d_inst.p;
     f.conns = c->d_conns.p;
     f.sc = c->sc.p;
+    f.ref = c->refs.p;
     f.ws = (float *)ws;
     f.stats = (float *)((char *)ws + c->off_stats);
     f.flags = flags;
@@ -1129,5 +1147,66 @@ extern "C" vadx_status vadx_analysis_kernel_time(vadx_ctx *c, int64_t *launches,
         c->an_timer.n[k] = 0;
         c->an_timer.ms[k] = 0.0;
     }
+    return VADX_OK;
+}
+
+// ------------------------------------------------------- fitness and ranking
+extern "C" vadx_status vadx_set_reference_fc(vadx_ctx *c, int32_t conn_id, const float *fc)
+{
+    if (!c) return VADX_E_ARG;
+    if (conn_id < 0 || conn_id >= (int32_t)c->conns.size()) return fail(c, VADX_E_ARG, "no such connectome");
+    HostConn &h = c->conns[(size_t)conn_id];
+    const int64_t nn = (int64_t)h.n * h.n;
+    if (!fc) {
+        h.ref_off = -1;
+        ++c->plan_epoch;
+        return upload_conns(c);
+    }
+    for (int64_t i = 0; i < nn; ++i)
+        if (!std::isfinite(fc[i])) return fail(c, VADX_E_ARG, "non-finite reference FC entry");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (h.ref_slot < 0) {
+        // grow the reference store, keeping the matrices already there
+        const int64_t need = c->total_ref + nn;
+        if ((size_t)need > c->refs.n) {
+            float *np = nullptr;
+            HIP_TRY(c, hipMalloc((void **)&np, sizeof(float) * (size_t)need));
+            if (c->refs.p && c->total_ref > 0) {
+                HIP_TRY(c, hipMemcpyAsync(np, c->refs.p, sizeof(float) * (size_t)c->total_ref,
+                                          hipMemcpyDeviceToDevice, c->stream));
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+            }
+            if (c->refs.p) (void)hipFree(c->refs.p);
+            c->refs.p = np;
+            c->refs.n = (size_t)need;
+        }
+        h.ref_slot = c->total_ref;
+        c->total_ref += nn;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->refs.p + h.ref_slot, fc, sizeof(float) * (size_t)nn,
+                              hipMemcpyHostToDevice, c->stream));
+    h.ref_off = h.ref_slot;
+    ++c->plan_epoch;                  // a recorded graph holds the old reference pointer
+    return upload_conns(c);
+}
+
+extern "C" vadx_status vadx_top_k(vadx_ctx *c, const float *score, int64_t n, int32_t k,
+                                  int64_t *idx, float *val)
+{
+    if (!c) return VADX_E_ARG;
+    if (n < 0 || k < 0 || (n > 0 && !score) || (k > 0 && !idx))
+        return fail(c, VADX_E_ARG, "bad top-k arguments");
+    if (k > 1024) return fail(c, VADX_E_UNSUPPORTED, "k above 1024");
+    if (k > n) return fail(c, VADX_E_ARG, "k above the number of scores");
+    if (k == 0) return VADX_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, c->topk_idx.ensure((size_t)k));
+    int64_t n_sel = 0;
+    std::string err;
+    vadx_status st = select_run(c->stream, c->sel, score, n, k, 0.f, 0u, c->topk_idx.p, nullptr, k,
+                                &n_sel, err);
+    if (st) return fail(c, st, "%s", err.c_str());
+    if (n_sel != k) return fail(c, VADX_E_ARG, "selection returned %lld of %d", (long long)n_sel, k);
+    HIP_TRY(c, launch_rank_sort(score, c->topk_idx.p, k, idx, val, c->stream));
     return VADX_OK;
 }

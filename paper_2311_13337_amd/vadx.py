@@ -33,7 +33,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
            "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze",
-           "vadx_analysis_kernel_time")
+           "vadx_analysis_kernel_time", "vadx_set_reference_fc", "vadx_top_k")
 ANALYSIS_KERNELS = ("an_transpose_kernel", "an_welch_kernel", "an_hilbert_kernel", "an_pli_kernel",
                     "an_ud_kernel", "an_final_kernel")
 ANALYSIS_NAMES = ("psd_fmax_hz", "psd_ampmax", "psd_slope_a", "psd_log10_b", "mean_pli",
@@ -83,7 +83,7 @@ class vadx_analysis(C.Structure):
 
 class vadx_stats(C.Structure):
     _fields_ = [(f, C.c_float) for f in STAT_NAMES] + [("flags", C.c_uint32),
-                                                        ("reserved", C.c_uint32)]
+                                                        ("fc_fit", C.c_float)]
 
 
 _lib = None
@@ -153,6 +153,8 @@ def lib():
                                          P(vadx_analysis_cfg), vp, C.c_size_t, vp, vp, vp]),
             "vadx_analyze": (st, [vp, P(vadx_analysis_cfg), vp, C.c_size_t, vp]),
             "vadx_analysis_kernel_time": (st, [vp, vp, vp]),
+            "vadx_set_reference_fc": (st, [vp, C.c_int32, vp]),
+            "vadx_top_k": (st, [vp, vp, C.c_int64, C.c_int32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -323,6 +325,22 @@ class Context:
             C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(out.data_ptr()),
             None if psd_out is None else C.c_void_p(psd_out.data_ptr()),
             None if pli_out is None else C.c_void_p(pli_out.data_ptr())))
+
+    def vadx_set_reference_fc(self, conn_id: int, fc=None):
+        if fc is None:
+            self._check(lib().vadx_set_reference_fc(self.h, conn_id, None))
+            return
+        a = np.ascontiguousarray(fc, np.float32)
+        self._check(lib().vadx_set_reference_fc(self.h, conn_id, _ptr(a)))
+
+    def vadx_top_k(self, score, k: int):
+        """score: device float32 tensor; returns (indices, scores) as device tensors."""
+        import torch
+        idx = torch.empty(max(k, 1), dtype=torch.int64, device=score.device)
+        val = torch.empty(max(k, 1), dtype=torch.float32, device=score.device)
+        self._check(lib().vadx_top_k(self.h, C.c_void_p(score.data_ptr()), score.numel(), k,
+                                     C.c_void_p(idx.data_ptr()), C.c_void_p(val.data_ptr())))
+        return idx[:k], val[:k]
 
     def vadx_analyze(self, cfg: "vadx_analysis_cfg", ws, out):
         self._check(lib().vadx_analyze(self.h, C.byref(cfg), C.c_void_p(ws.data_ptr()),

@@ -214,3 +214,37 @@ def test_analyze_instance_flat_and_mixed():
     assert r["ud_up_ms"] == pytest.approx(r["ud"][:, 0].sum() / r["ud"][:, 1].sum())
     # the instance spectrum is the mean of the region spectra
     np.testing.assert_allclose(r["mean_psd"], r["psd"].mean(axis=0), rtol=1e-15)
+
+
+def test_fc_fitness_against_scipy_and_invariances():
+    import scipy.stats
+    rng = np.random.default_rng(5)
+    n = 20
+    F = rng.uniform(-0.2, 0.9, (n, n))
+    F = (F + F.T) / 2
+    np.fill_diagonal(F, 1.0)
+    R = rng.uniform(-0.2, 0.9, (n, n))
+    R = (R + R.T) / 2
+    np.fill_diagonal(R, 7.0)                               # the diagonal takes no part
+    iu = np.triu_indices(n, 1)
+    want = scipy.stats.pearsonr(F[iu], R[iu])[0]
+    assert A.fc_fitness(F, R) == pytest.approx(want, abs=1e-13)
+    assert A.fc_fitness(F, 3.0 * R - 2.0) == pytest.approx(want, abs=1e-13)
+    assert A.fc_fitness(F, -R) == pytest.approx(-want, abs=1e-13)
+    assert A.fc_fitness(F, F) == pytest.approx(1.0, abs=1e-14)
+    assert A.fc_fitness(np.eye(n), R) == 0.0               # no variance off the diagonal
+    assert A.fc_fitness(np.eye(1), np.eye(1)) == 0.0
+
+
+def test_top_k_definition():
+    s = np.array([0.5, 2.0, 2.0, -1.0, 2.0, 0.5])
+    assert A.top_k(s, 4).tolist() == [1, 2, 4, 0]
+    assert A.top_k(s, 0).tolist() == []
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        v = rng.integers(0, 5, 40).astype(float)
+        k = int(rng.integers(1, 40))
+        got = A.top_k(v, k)
+        # brute force: sort pairs (-value, index)
+        want = [i for _, i in sorted((-v[i], i) for i in range(40))][:k]
+        assert got.tolist() == want
