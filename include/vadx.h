@@ -141,6 +141,19 @@ vadx_status vadx_set_batch(vadx_ctx *ctx, int64_t n_inst, const float *S, const 
  * have in a larger sweep reproduces exactly the runs of that sweep. */
 vadx_status vadx_set_noise_keys(vadx_ctx *ctx, int64_t n, const uint32_t *keys);
 
+/* Further sweep axes of the paper's vast exploration (Table 4) as
+ * per-instance values of model parameters: the noise weight w_noise (>= 0),
+ * the excitatory adaptation time constant tau_w_e (ms, > 0) and the external
+ * drives cF_ee, cF_ei, cF_ie, cF_ii (kHz, >= 0). values: host array of n =
+ * batch-size doubles (copied), or NULL to use the model's value for every
+ * instance; vadx_set_batch resets all of them to the model's. Instances whose
+ * populations see different drives (cF_ee != cF_ie or cF_ei != cF_ii) run the
+ * general transfer-function path; results of the others do not change.
+ * Takes effect at the next vadx_plan. */
+enum { VADX_P_W_NOISE = 0, VADX_P_TAU_W_E = 1, VADX_P_CF_EE = 2, VADX_P_CF_EI = 3,
+       VADX_P_CF_IE = 4, VADX_P_CF_II = 5 };
+vadx_status vadx_set_instance_param(vadx_ctx *ctx, int32_t param, int64_t n, const double *values);
+
 /* Chooses up to 1024 instances whose first run->n_trace_steps states are
  * recorded (trace slot i = inst[i]). n = 0 clears the selection. */
 vadx_status vadx_set_trace(vadx_ctx *ctx, int64_t n, const int64_t *inst);

@@ -88,7 +88,7 @@ def lib():
         L.oracle_step_region.restype = C.c_uint32
         vp = C.c_void_p
         L.oracle_run.argtypes = [P(Model), P(RunCfg), C.c_int, dp, dp, C.c_int64, fp, fp, fp, fp,
-                                 up, vp, dp, vp, vp, vp, vp, up, C.c_int]
+                                 up, vp, vp, dp, vp, vp, vp, vp, up, C.c_int]
         assert L.oracle_model_size() == C.sizeof(Model), "oracle model layout mismatch"
         _lib = L
     return _lib
@@ -191,13 +191,19 @@ def run(m: Model, run_cfg, conn, batch, inst_ids=None, n_trace_steps=None, want_
         "flags": np.zeros(ni, np.uint32),
     }
     init = None if init_state is None else np.ascontiguousarray(init_state, np.float64)
+    extra = None
+    if getattr(batch, "extra", None):
+        names = ("w_noise", "tau_w_e", "cF_ee", "cF_ei", "cF_ie", "cF_ii")
+        extra = np.empty((ni, 6))
+        for j, name in enumerate(names):
+            extra[:, j] = batch.extra[name] if name in batch.extra else getattr(m, name)
     if n_threads is None:
         n_threads = os.cpu_count() or 1
     rc = lib().oracle_run(C.byref(m), C.byref(r), n, np.ascontiguousarray(conn.weights, np.float64),
                           np.ascontiguousarray(conn.tract_mm, np.float64), ni,
                           np.ascontiguousarray(batch.S), np.ascontiguousarray(batch.b_e),
                           np.ascontiguousarray(batch.a_e), np.ascontiguousarray(batch.v), ids,
-                          _ptr(init), out["final"], _ptr(out["samples"]), _ptr(out["trace"]),
+                          _ptr(init), _ptr(extra), out["final"], _ptr(out["samples"]), _ptr(out["trace"]),
                           _ptr(out["fc"]), _ptr(out["stats"]), out["flags"], int(n_threads))
     if rc != 0:
         raise ValueError("oracle_run rejected its arguments")

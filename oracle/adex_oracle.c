@@ -531,13 +531,25 @@ typedef struct {
     double *stats;         /* [inst][6] or NULL */
     uint32_t *flags;       /* [inst] */
     const double *init_state; /* [8] or NULL: uniform initial state override */
+    const double *extra;   /* [inst][6] or NULL: per-instance w_noise, tau_w_e, cF_ee, cF_ei,
+                              cF_ie, cF_ii (the further sweep axes of Table 4) */
     int64_t next;
     pthread_mutex_t mu;
 } run_job;
 
 static void run_instance(run_job *J, int64_t q)
 {
-    const or_model *m = J->m;
+    or_model mi = *J->m;   /* the model with this instance's parameters */
+    if (J->extra) {
+        const double *e = J->extra + q * 6;
+        mi.w_noise = e[0];
+        mi.tau_w_e = e[1];
+        mi.cF_ee = e[2];
+        mi.cF_ei = e[3];
+        mi.cF_ie = e[4];
+        mi.cF_ii = e[5];
+    }
+    const or_model *m = &mi;
     const or_run *r = J->r;
     const int n = J->n;
     const int64_t ns = (r->n_steps - r->transient_steps) / r->tavg_steps;
@@ -624,7 +636,8 @@ static void *run_worker(void *arg)
    final_state and flags. */
 int oracle_run(const or_model *m, const or_run *r, int n, const double *w_raw, const double *L,
                int64_t n_inst, const float *S, const float *b_e, const float *a_e, const float *v,
-               const uint32_t *inst_id, const double *init_state, double *final_state,
+               const uint32_t *inst_id, const double *init_state, const double *extra,
+               double *final_state,
                double *samples, double *trace, double *fc, double *stats, uint32_t *flags,
                int n_threads)
 {
@@ -634,7 +647,7 @@ int oracle_run(const or_model *m, const or_run *r, int n, const double *w_raw, c
     J.m = m; J.r = r; J.n = n; J.w_raw = w_raw; J.L = L;
     J.S = S; J.b_e = b_e; J.a_e = a_e; J.v = v; J.inst_id = inst_id; J.n_inst = n_inst;
     J.final_state = final_state; J.samples = samples; J.trace = trace; J.fc = fc;
-    J.stats = stats; J.flags = flags; J.init_state = init_state;
+    J.stats = stats; J.flags = flags; J.init_state = init_state; J.extra = extra;
     pthread_mutex_init(&J.mu, NULL);
     if (n_threads < 1) n_threads = 1;
     pthread_t *th = malloc(sizeof(pthread_t) * n_threads);

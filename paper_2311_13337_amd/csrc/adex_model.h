@@ -402,19 +402,41 @@ VADX_HD QJet<T> transfer(const KModel &M, int pop, const TFShared<T> &g, const C
     }
 }
 
-// Per-instance parameters.
-template <class T> struct InstParams { T S, b_e, a_e; };
+// Parameters of one instance (the axes of a sweep, Table 4): spike-frequency
+// and subthreshold adaptation b_e, a_e, noise weight, 1/tau_w of the
+// excitatory population and the external drives c_F (population, input).
+template <class T> struct InstModel {
+    T be, ae, w_noise, inv_tauw_e;
+    T cF[2][2];
+};
+
+// The instance parameters equal to the model's, with b_e and a_e given.
+template <class T> VADX_HD InstModel<T> inst_model(const KModel &M, T be, T ae)
+{
+    InstModel<T> P;
+    P.be = be;
+    P.ae = ae;
+    P.w_noise = T(M.w_noise);
+    P.inv_tauw_e = T(M.inv_tauw[0]);
+    P.cF[0][0] = T(M.cF[0][0]);
+    P.cF[0][1] = T(M.cF[0][1]);
+    P.cF[1][0] = T(M.cF[1][0]);
+    P.cF[1][1] = T(M.cF[1][1]);
+    return P;
+}
 
 // Drift of one region's 8 states given its coupling input c (eq. 1-4).
+// VAR & kVarSame requires P.cF[0] == P.cF[1] (both populations see the same inputs).
 template <int VAR, class T>
-VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
+VADX_HD void drift(const KModel &M, const T X[8], T c, const InstModel<T> &P, T dX[8])
 {
     const T E = X[0], I = X[1], Cee = X[2], Cei = X[3], Cii = X[4];
-    T exc = E + c + T(M.w_noise) * X[7];
-    T xe0 = maxf_(exc + T(M.cF[0][0]), T(M.x_floor));
-    T xi0 = maxf_(I + T(M.cF[0][1]), T(M.x_floor));
-    T xe1 = maxf_(exc + T(M.cF[1][0]), T(M.x_floor));
-    T xi1 = maxf_(I + T(M.cF[1][1]), T(M.x_floor));
+    const T be = P.be, ae = P.ae;
+    T exc = E + c + P.w_noise * X[7];
+    T xe0 = maxf_(exc + P.cF[0][0], T(M.x_floor));
+    T xi0 = maxf_(I + P.cF[0][1], T(M.x_floor));
+    T xe1 = maxf_(exc + P.cF[1][0], T(M.x_floor));
+    T xi1 = maxf_(I + P.cF[1][1], T(M.x_floor));
     // the covariance of the inputs (xe, xi) is that of the rates (E, I)
     Cov<T> C;
     C.ee = Cee;
@@ -448,7 +470,7 @@ VADX_HD void drift(const KModel &M, const T X[8], T c, T be, T ae, T dX[8])
     dX[4] = iT * fmaf_(Fi.v * (iT - Fi.v), T(M.invNi),
                        fmaf_(fi, fi, T(2) * (fmaf_(Cii, Fi.b, Cei * Fi.a) - Cii)));
     // eq. 3 (AdEx form, subthreshold term over tau_w)
-    dX[5] = fmaf_(be, E, T(M.inv_tauw[0]) * fmaf_(ae, muVe - T(M.EL[0]), -X[5]));
+    dX[5] = fmaf_(be, E, P.inv_tauw_e * fmaf_(ae, muVe - T(M.EL[0]), -X[5]));
     dX[6] = fmaf_(T(M.b_i), I, T(M.inv_tauw[1]) * fmaf_(T(M.a_i), muVi - T(M.EL[1]), -X[6]));
     // eq. 4, deterministic part
     dX[7] = -X[7] * T(M.inv_tauOU);
@@ -494,12 +516,13 @@ enum { kStepNonfinite = 1u, kStepClamp = 2u };
 // in S (double), so the rounding of the state does not build up over the
 // run. gdw is the OU increment (sigma/tau_OU) sqrt(dt) z. Returns kStep* flags.
 template <int VAR, class T, class S>
-VADX_HD uint32_t step_region(const KModel &M, int integrator, S dt, S X[8], T c, T be, T ae, S gdw)
+VADX_HD uint32_t step_region(const KModel &M, int integrator, S dt, S X[8], T c,
+                             const InstModel<T> &P, S gdw)
 {
     T xf[8], f0[8], f1[8];
     S Xt[8];
     for (int q = 0; q < 8; ++q) xf[q] = T(X[q]);
-    drift<VAR>(M, xf, c, be, ae, f0);
+    drift<VAR>(M, xf, c, P, f0);
     if (integrator == 1) {
         const uint32_t nf = finite_(f0[0] + f0[1]) ? 0u : kStepNonfinite;
         for (int q = 0; q < 8; ++q) X[q] = X[q] + dt * S(f0[q]);
@@ -510,7 +533,7 @@ VADX_HD uint32_t step_region(const KModel &M, int integrator, S dt, S X[8], T c,
     Xt[7] = Xt[7] + gdw;
     bool hit = project(M, Xt);
     for (int q = 0; q < 8; ++q) xf[q] = T(Xt[q]);
-    drift<VAR>(M, xf, c, be, ae, f1);
+    drift<VAR>(M, xf, c, P, f1);
     const uint32_t nf = finite_((f0[0] + f0[1]) + (f1[0] + f1[1])) ? 0u : kStepNonfinite;
     const S hdt = S(0.5) * dt;
     for (int q = 0; q < 8; ++q) X[q] = X[q] + hdt * S(f0[q] + f1[q]);

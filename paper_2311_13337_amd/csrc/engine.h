@@ -16,6 +16,8 @@ constexpr int kMaxBlock = 32;
 // One instance = one parameter combination on one connectome.
 struct InstDev {
     float S, be, ae;
+    float w_noise, inv_tauw_e;  // noise weight, 1/tau_w of the excitatory population
+    float cF[4];                // external drives c_F: ee, ei, ie, ii
     int32_t n;          // regions
     int32_t D;          // ring depth in steps
     int32_t conn;       // connectome

@@ -172,7 +172,16 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
     }
     __syncthreads();   // initial rings visible to all lanes
 
-    const float S = active ? I.S : 0.f, be = active ? I.be : 0.f, ae = active ? I.ae : 0.f;
+    const float S = active ? I.S : 0.f;
+    InstModel<float> P;
+    P.be = active ? I.be : 0.f;
+    P.ae = active ? I.ae : 0.f;
+    P.w_noise = active ? I.w_noise : 0.f;
+    P.inv_tauw_e = active ? I.inv_tauw_e : 0.f;
+    P.cF[0][0] = active ? I.cF[0] : 0.f;
+    P.cF[0][1] = active ? I.cF[1] : 0.f;
+    P.cF[1][0] = active ? I.cF[2] : 0.f;
+    P.cF[1][1] = active ? I.cF[3] : 0.f;
     const int D = active ? I.D : 1;
     const int Dp = active ? I.Dp : 1;
     int nm = active ? (int)(n_begin % D) : 0;   // n0 mod D
@@ -223,7 +232,7 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                     normals4(a.seed, I.id, (uint32_t)(n >> 2), (uint32_t)k, z4);
                 const float z = r == 0 ? z4[0] : (r == 1 ? z4[1] : (r == 2 ? z4[2] : z4[3]));
                 const float c = cbuf[b * nthr + tid];
-                fl |= step_region<VAR>(a.M, a.integrator, a.dt, X, c, be, ae,
+                fl |= step_region<VAR>(a.M, a.integrator, a.dt, X, c, P,
                                        a.gdw_scale * (double)z);
                 // history of E: slot (n + 1) mod D, and its mirror
                 wm += 1;

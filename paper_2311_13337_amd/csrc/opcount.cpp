@@ -67,11 +67,12 @@ extern "C" vadx_status vadx_region_step_ops(int32_t integrator, double *flop32, 
     CD X[8] = {CD(0.004), CD(0.01), CD(2e-6), CD(4e-6), CD(1e-5), CD(20.0), CD(0.0), CD(1e-4)};
     const CD dt(0.1), gdw(1e-5);
     const CF c(1e-3f), be(30.f), ae(2.f);
+    const InstModel<CF> P = inst_model<CF>(M, be, ae);
     switch (model_variant(M)) {
-    case 0: step_region<0, CF, CD>(M, integrator, dt, X, c, be, ae, gdw); break;
-    case 1: step_region<1, CF, CD>(M, integrator, dt, X, c, be, ae, gdw); break;
-    case 2: step_region<2, CF, CD>(M, integrator, dt, X, c, be, ae, gdw); break;
-    default: step_region<3, CF, CD>(M, integrator, dt, X, c, be, ae, gdw); break;
+    case 0: step_region<0, CF, CD>(M, integrator, dt, X, c, P, gdw); break;
+    case 1: step_region<1, CF, CD>(M, integrator, dt, X, c, P, gdw); break;
+    case 2: step_region<2, CF, CD>(M, integrator, dt, X, c, P, gdw); break;
+    default: step_region<3, CF, CD>(M, integrator, dt, X, c, P, gdw); break;
     }
     // per-step extras of the kernel: coupling scale S*c, OU increment gdw*z, the
     // running time average, and one quarter of a Box-Muller pair evaluation

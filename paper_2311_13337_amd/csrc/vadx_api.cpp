@@ -90,6 +90,8 @@ struct vadx_ctx {
     std::vector<float> S, be, ae, v;
     std::vector<int32_t> conn_of;
     std::vector<uint32_t> noise_key;     // Philox key word per instance (default: batch index)
+    std::vector<double> iparam[6];       // per-instance model parameters (empty: the model's)
+    bool batch_same = true;              // every instance's populations see the same inputs
     std::vector<int64_t> traced;
     // plan
     bool planned = false;
@@ -376,6 +378,7 @@ vadx_status vadx_set_batch(vadx_ctx *c, int64_t n, const float *S, const float *
     if (conn) c->conn_of.assign(conn, conn + n);
     c->noise_key.resize((size_t)n);
     for (int64_t i = 0; i < n; ++i) c->noise_key[(size_t)i] = (uint32_t)i;
+    for (auto &p : c->iparam) p.clear();
     c->traced.clear();
     c->planned = false;
     c->ran = false;
@@ -511,6 +514,15 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         const HostConn &hc = c->conns[c->conn_of[i]];
         InstDev &d = c->h_inst[i];
         d.S = c->S[i]; d.be = c->be[i]; d.ae = c->ae[i];
+        auto ip = [&](int p, double model_value) {
+            return c->iparam[p].empty() ? model_value : c->iparam[p][(size_t)i];
+        };
+        d.w_noise = (float)ip(VADX_P_W_NOISE, c->model.w_noise);
+        d.inv_tauw_e = (float)(1.0 / ip(VADX_P_TAU_W_E, c->model.tau_w_e));
+        d.cF[0] = (float)ip(VADX_P_CF_EE, c->model.cF_ee);
+        d.cF[1] = (float)ip(VADX_P_CF_EI, c->model.cF_ei);
+        d.cF[2] = (float)ip(VADX_P_CF_IE, c->model.cF_ie);
+        d.cF[3] = (float)ip(VADX_P_CF_II, c->model.cF_ii);
         d.n = hc.n;
         d.D = (int32_t)(dmax[i] + blk[i] + 1);
         d.Dp = d.D + blk[i] - 1;
@@ -524,6 +536,9 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         d.samp_off = f_samp; f_samp += (ns > 0 ? ns : 0) * hc.n;
         d.fc_off = f_fc; f_fc += (int64_t)hc.n * hc.n;
     }
+    c->batch_same = true;
+    for (const auto &d : c->h_inst)
+        if (!(d.cF[0] == d.cF[2] && d.cF[1] == d.cF[3])) c->batch_same = false;
     if (r->n_trace_steps > 0)
         for (int64_t t : c->traced) {
             InstDev &d = c->h_inst[t];
@@ -588,6 +603,7 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     HIP_TRY(c, launch_fill_u32(flags, ni, 0u, st));
     IntegrateArgs a{};
     a.M = make_kmodel(c->model);
+    a.M.same_inputs = c->batch_same ? 1 : 0;
     a.inst = c->d_inst.p;
     a.perm = c->d_perm.p;
     a.groups = c->d_groups.p;
@@ -1208,5 +1224,28 @@ extern "C" vadx_status vadx_top_k(vadx_ctx *c, const float *score, int64_t n, in
     if (st) return fail(c, st, "%s", err.c_str());
     if (n_sel != k) return fail(c, VADX_E_ARG, "selection returned %lld of %d", (long long)n_sel, k);
     HIP_TRY(c, launch_rank_sort(score, c->topk_idx.p, k, idx, val, c->stream));
+    return VADX_OK;
+}
+
+extern "C" vadx_status vadx_set_instance_param(vadx_ctx *c, int32_t param, int64_t n,
+                                               const double *values)
+{
+    if (!c) return VADX_E_ARG;
+    if (param < 0 || param >= 6) return fail(c, VADX_E_ARG, "unknown parameter %d", param);
+    if (n != (int64_t)c->S.size()) return fail(c, VADX_E_ARG, "n must equal the batch size");
+    if (!values) {
+        c->iparam[param].clear();
+    } else {
+        for (int64_t i = 0; i < n; ++i) {
+            const double v = values[i];
+            const bool ok = param == VADX_P_TAU_W_E ? (std::isfinite(v) && v > 0.0)
+                                                    : (std::isfinite(v) && v >= 0.0);
+            if (!ok) return fail(c, VADX_E_ARG, "parameter %d of instance %lld out of range", param,
+                                 (long long)i);
+        }
+        c->iparam[param].assign(values, values + n);
+    }
+    c->planned = false;
+    c->ran = false;
     return VADX_OK;
 }

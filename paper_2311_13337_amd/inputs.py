@@ -74,13 +74,17 @@ class Batch:
     a_e: np.ndarray
     v: np.ndarray
     conn: np.ndarray  # int32 connectome index per instance
+    # further per-instance model parameters (Table 4 axes), name -> float64 array:
+    # w_noise, tau_w_e, cF_ee, cF_ei, cF_ie, cF_ii; absent names take the model's value
+    extra: dict = dataclasses.field(default_factory=dict)
 
     def __len__(self) -> int:
         return int(self.S.shape[0])
 
     def subset(self, idx) -> "Batch":
         idx = np.asarray(idx)
-        return Batch(self.S[idx], self.b_e[idx], self.a_e[idx], self.v[idx], self.conn[idx])
+        return Batch(self.S[idx], self.b_e[idx], self.a_e[idx], self.v[idx], self.conn[idx],
+                     {k: np.asarray(v)[idx] for k, v in self.extra.items()})
 
 
 def _batch(S, b_e, a_e, v, conn=None) -> Batch:
@@ -220,3 +224,27 @@ def synthetic_rate_series(n_inst: int, n: int, n_samples: int, seed: int = 5,
                 x = 3.85e-3 + rng.standard_normal(n_samples) * 5e-5
             out[i, :, k] = np.maximum(x, 0.0)
     return out
+
+
+# The paper's vast exploration (Table 4): ten axes with their ranges and
+# resolutions (g is the coupling S; the weight noise scales the OU input).
+TABLE4_AXES = (("S", 0.1, 0.9, 8), ("b_e", 0.0, 100.0, 8), ("w_noise", 1e-9, 1e-4, 4),
+               ("v", 1.0, 7.0, 4), ("tau_w_e", 250.0, 750.0, 4), ("a_e", -10.0, 20.0, 4),
+               ("cF_ee", 0.3e-3, 0.5e-3, 2), ("cF_ei", 0.0, 0.5e-3, 2),
+               ("cF_ie", 0.3e-3, 0.5e-3, 2), ("cF_ii", 0.0, 0.5e-3, 2))
+
+
+def grid_table4(idx=None) -> Batch:
+    """Points of the ten-axis Table 4 grid (262,144 points; `idx` selects a
+    subset by flat index, axis order as listed, last axis fastest). External
+    drives are given in kHz as the model takes them."""
+    axes = [np.linspace(lo, hi, n) for _, lo, hi, n in TABLE4_AXES]
+    shape = tuple(len(a) for a in axes)
+    total = int(np.prod(shape))
+    idx = np.arange(total) if idx is None else np.asarray(idx, np.int64)
+    coords = np.unravel_index(idx, shape)
+    vals = {name: axes[d][coords[d]] for d, (name, _, _, _) in enumerate(TABLE4_AXES)}
+    b = _batch(vals["S"], vals["b_e"], vals["a_e"], vals["v"])
+    b.extra = {k: np.asarray(vals[k], np.float64)
+               for k in ("w_noise", "tau_w_e", "cF_ee", "cF_ei", "cF_ie", "cF_ii")}
+    return b

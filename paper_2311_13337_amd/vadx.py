@@ -33,7 +33,9 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
            "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze",
-           "vadx_analysis_kernel_time", "vadx_set_reference_fc", "vadx_top_k")
+           "vadx_analysis_kernel_time", "vadx_set_reference_fc", "vadx_top_k",
+           "vadx_set_instance_param")
+INSTANCE_PARAMS = {"w_noise": 0, "tau_w_e": 1, "cF_ee": 2, "cF_ei": 3, "cF_ie": 4, "cF_ii": 5}
 ANALYSIS_KERNELS = ("an_transpose_kernel", "an_welch_kernel", "an_hilbert_kernel", "an_pli_kernel",
                     "an_ud_kernel", "an_final_kernel")
 ANALYSIS_NAMES = ("psd_fmax_hz", "psd_ampmax", "psd_slope_a", "psd_log10_b", "mean_pli",
@@ -155,6 +157,7 @@ def lib():
             "vadx_analysis_kernel_time": (st, [vp, vp, vp]),
             "vadx_set_reference_fc": (st, [vp, C.c_int32, vp]),
             "vadx_top_k": (st, [vp, vp, C.c_int64, C.c_int32, vp, vp]),
+            "vadx_set_instance_param": (st, [vp, C.c_int32, C.c_int64, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -254,6 +257,15 @@ class Context:
     def vadx_set_noise_keys(self, keys):
         a = np.ascontiguousarray(keys, np.uint32)
         self._check(lib().vadx_set_noise_keys(self.h, a.shape[0], _ptr(a) if a.size else None))
+
+    def vadx_set_instance_param(self, name: str, values=None):
+        p = INSTANCE_PARAMS[name]
+        if values is None:
+            n = len(self._keep[0][0])
+            self._check(lib().vadx_set_instance_param(self.h, p, n, None))
+            return
+        a = np.ascontiguousarray(values, np.float64)
+        self._check(lib().vadx_set_instance_param(self.h, p, a.shape[0], _ptr(a)))
 
     def vadx_set_trace(self, inst):
         a = np.ascontiguousarray(inst, np.int64)
@@ -419,6 +431,8 @@ class Sweep:
         self.ctx.vadx_set_batch(batch.S, batch.b_e, batch.a_e, batch.v, conn)
         if noise_keys is not None:
             self.ctx.vadx_set_noise_keys(noise_keys)
+        for name, values in (getattr(batch, "extra", None) or {}).items():
+            self.ctx.vadx_set_instance_param(name, values)
 
     def plan(self, run: vadx_run, trace=()):
         self.ctx.vadx_set_trace(list(trace))

@@ -39,10 +39,10 @@ void mh_drift(const vadx_model *m, const float *X, float c, float be, float ae, 
 {
     KModel k = make_kmodel(*m);
     switch (model_variant(k)) {
-    case 0: drift<0>(k, X, c, be, ae, dX); break;
-    case 1: drift<1>(k, X, c, be, ae, dX); break;
-    case 2: drift<2>(k, X, c, be, ae, dX); break;
-    default: drift<3>(k, X, c, be, ae, dX); break;
+    case 0: drift<0>(k, X, c, inst_model(k, be, ae), dX); break;
+    case 1: drift<1>(k, X, c, inst_model(k, be, ae), dX); break;
+    case 2: drift<2>(k, X, c, inst_model(k, be, ae), dX); break;
+    default: drift<3>(k, X, c, inst_model(k, be, ae), dX); break;
     }
 }
 
@@ -51,10 +51,10 @@ int mh_step(const vadx_model *m, int integrator, double dt, double *X, float c, 
 {
     KModel k = make_kmodel(*m);
     switch (model_variant(k)) {
-    case 0: return step_region<0>(k, integrator, dt, X, c, be, ae, gdw);
-    case 1: return step_region<1>(k, integrator, dt, X, c, be, ae, gdw);
-    case 2: return step_region<2>(k, integrator, dt, X, c, be, ae, gdw);
-    default: return step_region<3>(k, integrator, dt, X, c, be, ae, gdw);
+    case 0: return step_region<0>(k, integrator, dt, X, c, inst_model(k, be, ae), gdw);
+    case 1: return step_region<1>(k, integrator, dt, X, c, inst_model(k, be, ae), gdw);
+    case 2: return step_region<2>(k, integrator, dt, X, c, inst_model(k, be, ae), gdw);
+    default: return step_region<3>(k, integrator, dt, X, c, inst_model(k, be, ae), gdw);
     }
 }
 

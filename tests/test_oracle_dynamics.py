@@ -318,3 +318,28 @@ def test_inhibitory_adaptation_stays_zero(oracle):
     r = oracle.run(m, inputs.RunConfig(n_steps=500, n_trace_steps=500), conn,
                    inputs.grid_small().subset([0, 7]))
     assert np.all(r["trace"][:, :, WI, :] == 0.0)
+
+
+def test_instance_parameters_equal_model_parameters(oracle):
+    """The per-instance sweep axes (noise weight, tau_w_e, external drives) act
+    exactly as the same values in the model: two instances with their own values
+    reproduce, bit for bit, runs of models that carry those values."""
+    conn = inputs.synthetic_connectome(6, seed=11)
+    cfg = inputs.RunConfig(n_steps=300, transient_steps=0, n_trace_steps=300)
+    b = inputs.grid_small().subset([1, 6])
+    vals = [dict(w_noise=3e-4, tau_w_e=300.0, cF_ee=4e-4, cF_ei=1e-4, cF_ie=3e-4, cF_ii=0.0),
+            dict(w_noise=1e-9, tau_w_e=700.0, cF_ee=3e-4, cF_ei=5e-4, cF_ie=5e-4, cF_ii=2e-4)]
+    b.extra = {k: np.array([v[k] for v in vals]) for k in vals[0]}
+    r = oracle.run(oracle.model("literature-B"), cfg, conn, b, n_threads=1)
+    for q in range(2):
+        m = oracle.model("literature-B", **vals[q])
+        one = b.subset([q])
+        one.extra = {}
+        r1 = oracle.run(m, cfg, conn, one, inst_ids=[q], n_threads=1)
+        assert np.array_equal(r["trace"][q], r1["trace"][0])
+        assert np.array_equal(r["fc"][q], r1["fc"][0])
+    # and they matter: the run differs from the default model's
+    b0 = b.subset([0, 1])
+    b0.extra = {}
+    r0 = oracle.run(oracle.model("literature-B"), cfg, conn, b0, n_threads=1)
+    assert not np.array_equal(r["trace"], r0["trace"])
