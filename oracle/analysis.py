@@ -2,7 +2,10 @@
 from the stored excitatory rate samples of one instance: the power spectral
 density with its peak and its fit to b / f^a, the phase lag index between
 regions, and the durations of Up and Down states. (mean_FC, the fourth metric
-of Table 2, is the FC mean of the main oracle.)
+of Table 2, is the FC mean of the main oracle.) Also the fitness against a
+reference FC and the ranking of a grid search (Section 2.4), and the
+Balloon-Windkessel BOLD signal the paper's GPU kernel computes (Section 2.4,
+after Stephan et al. 2007).
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and the CPU-baseline leg of
 ``bench.py``; never by the product path. It shares no code with the GPU
@@ -250,3 +253,65 @@ def analyze_instance(samples_khz: np.ndarray, period_ms: float, window: int = 0,
     if with_ambiguity:
         out["pli_ambiguous"] = pli_ambiguous(Z, with_ambiguity)
     return out
+
+
+# Balloon-Windkessel haemodynamics (Friston et al. 2000, as compared in Stephan
+# et al. 2007): time in s; kappa, gamma in 1/s; tau0 in s.
+BOLD_DEFAULTS = dict(kappa=0.65, gamma=0.41, tau0=0.98, alpha=0.32, E0=0.34, V0=0.02,
+                     k1=7 * 0.34, k2=2.0, k3=2 * 0.34 - 0.2, tr_ms=2000.0)
+
+
+def bold_rhs(x, z, p):
+    """d/dt of (s, f, v, q) for neural input z; x: [4, n]."""
+    s, f, v, q = x
+    vpow = v ** (1.0 / p["alpha"])
+    ds = z - p["kappa"] * s - p["gamma"] * (f - 1.0)
+    df = s
+    dv = (f - vpow) / p["tau0"]
+    dq = (f * (1.0 - (1.0 - p["E0"]) ** (1.0 / f)) / p["E0"] - vpow * q / v) / p["tau0"]
+    return np.stack([ds, df, dv, dq])
+
+
+def bold_signal(x, p):
+    s, f, v, q = x
+    return p["V0"] * (p["k1"] * (1.0 - q) + p["k2"] * (1.0 - q / v) + p["k3"] * (1.0 - v))
+
+
+def bold_series(samples_khz: np.ndarray, period_ms: float, **over) -> np.ndarray:
+    """BOLD of every region from its rate samples [ns][n] (kHz: the neural
+    input z is the excitatory rate in the model's unit, held over each sample
+    interval). Readings: classical Runge-Kutta (RK4) with the sample period as
+    the step, from rest (s = 0, f = v = q = 1); the signal sampled at
+    t = m TR, m = 1 .. floor(ns period / TR). Returns [n_tr][n]."""
+    p = dict(BOLD_DEFAULTS, **over)
+    z = np.asarray(samples_khz, np.float64)
+    ns, n = z.shape
+    h = period_ms / 1000.0
+    x = np.zeros((4, n))
+    x[1:] = 1.0
+    steps_per_tr = p["tr_ms"] / period_ms
+    n_tr = int(np.floor(ns * period_ms / p["tr_ms"] + 1e-9))
+    out = np.zeros((n_tr, n))
+    m = 0
+    for t in range(ns):
+        zt = z[t]
+        k1 = bold_rhs(x, zt, p)
+        k2 = bold_rhs(x + 0.5 * h * k1, zt, p)
+        k3 = bold_rhs(x + 0.5 * h * k2, zt, p)
+        k4 = bold_rhs(x + h * k3, zt, p)
+        x = x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        # after sample t the clock reads (t + 1) periods
+        while m < n_tr and (t + 1) >= round((m + 1) * steps_per_tr):
+            out[m] = bold_signal(x, p)
+            m += 1
+    return out
+
+
+def bold_fixed_point(z: float, **over):
+    """Steady state (s, f, v, q) and BOLD for a constant input z."""
+    p = dict(BOLD_DEFAULTS, **over)
+    f = 1.0 + z / p["gamma"]
+    v = f ** p["alpha"]
+    q = v * (1.0 - (1.0 - p["E0"]) ** (1.0 / f)) / p["E0"]
+    x = np.array([0.0, f, v, q])
+    return x, float(bold_signal(x, p))

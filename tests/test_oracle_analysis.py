@@ -248,3 +248,44 @@ def test_top_k_definition():
         # brute force: sort pairs (-value, index)
         want = [i for _, i in sorted((-v[i], i) for i in range(40))][:k]
         assert got.tolist() == want
+
+
+def test_bold_rest_and_fixed_point():
+    """At rest (z = 0) everything stays at (0, 1, 1, 1) and the BOLD is 0; under
+    a constant input the Runge-Kutta run converges to the closed-form fixed
+    point f = 1 + z/gamma, v = f^alpha, q = v (1 - (1 - E0)^(1/f)) / E0."""
+    z0 = np.zeros((3000, 2))
+    assert np.all(A.bold_series(z0, 1.0) == 0.0)
+    z = np.full((12000, 2), 0.004)                     # 4 Hz for 120 s in 10-ms samples
+    y = A.bold_series(z, 10.0, tr_ms=1000.0)
+    x_star, y_star = A.bold_fixed_point(0.004)
+    assert y.shape == (120, 2)
+    assert y[-1, 0] == pytest.approx(y_star, rel=1e-6)
+    # the fixed point solves the equations
+    np.testing.assert_allclose(A.bold_rhs(x_star[:, None], 0.004, A.BOLD_DEFAULTS)[:, 0], 0.0,
+                               atol=1e-15)
+
+
+def test_bold_rk4_is_fourth_order():
+    """Halving the step cuts the error of RK4 by 16 (input held piecewise
+    constant: a smooth input sampled finely enough that the hold error stays
+    below the integration error is not needed -- the same held input is used
+    at both steps by repeating each sample)."""
+    rng = np.random.default_rng(2)
+    base = 0.004 + 0.003 * np.sin(np.arange(400) / 15.0)[:, None] * np.ones((1, 3)) \
+        + 0.0005 * rng.standard_normal((400, 3))
+    def run(rep, period):
+        z = np.repeat(base, rep, axis=0)
+        return A.bold_series(z, period, tr_ms=400.0 * rep * period / 4)
+    ref = run(64, 100.0 / 64)
+    e1 = np.abs(run(1, 100.0) - ref).max()
+    e2 = np.abs(run(2, 50.0) - ref).max()
+    assert 12 < e1 / e2 < 20
+
+
+def test_bold_sampling_times():
+    z = np.full((5000, 1), 0.002)
+    y = A.bold_series(z, 1.0, tr_ms=720.0)
+    assert y.shape == (6, 1)                           # 0.72 .. 4.32 s
+    y2 = A.bold_series(z[:720 * 3], 1.0, tr_ms=720.0)
+    np.testing.assert_array_equal(y[:3], y2)
