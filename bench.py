@@ -292,6 +292,19 @@ def analysis_line(sw, conns, batch, cfg, args):
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": MI355X_HBM_GBPS, "unit": "GB/s",
                 "frac": round(ach / MI355X_HBM_GBPS, 4)}
     roof["kernel"] = dom
+    # BOLD of the same samples (Balloon-Windkessel, one thread per region)
+    bcfg = vadx.vadx_bold_defaults()
+    n_tr = int(ns * cfg.tavg_steps * cfg.dt_ms // bcfg.tr_ms)
+    bout = torch.empty(max(R * n_tr, 1), dtype=torch.float32, device="cuda:0")
+    ctx.vadx_bold(bcfg, bout)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.vadx_bold(bcfg, bout)
+    e1.record()
+    torch.cuda.synchronize()
+    bold_ms = e0.elapsed_time(e1) / reps
+    del bout
     # the oracle on synthetic series of the same shape (bounded sample)
     from oracle import analysis as oa
 
@@ -304,6 +317,9 @@ def analysis_line(sw, conns, batch, cfg, args):
     return {"metric": "analysed instances per s", "value": round(n_inst / (ms / 1000.0), 1),
             "ms_per_pass": round(ms, 3), "instances": n_inst, "regions": R, "window": Na,
             "segment": L, "kernels": kernels, "roofline": roof,
+            "bold": {"ms_per_pass": round(bold_ms, 3), "samples_per_region": ns,
+                     "rk4_steps_per_s": round(R * ns / (bold_ms / 1000.0), 1),
+                     "tr_ms": bcfg.tr_ms},
             "finite": bool(np.isfinite(res["psd_slope_a"]).all() and np.isfinite(res["mean_pli"]).all()),
             "mean_pli_mean": round(float(res["mean_pli"].mean()), 4),
             "cpu_oracle": {"s_per_instance": round(cpu_s, 4), "cores": 1, "kind": "oracle",

@@ -408,6 +408,33 @@ vadx_status vadx_analyze(vadx_ctx *ctx, const vadx_analysis_cfg *cfg, void *ws, 
  * since the last call (which resets them). Waits for the recorded events. */
 vadx_status vadx_analysis_kernel_time(vadx_ctx *ctx, int64_t *launches, double *ms);
 
+/* BOLD signal (Section 2.4's Balloon-Windkessel kernel; haemodynamics after
+ * Stephan et al. 2007, classical output coefficients): per region, with the
+ * neural input z = the excitatory rate sample (kHz) held over each sample
+ * interval, from rest (s = 0, f = v = q = 1):
+ *   ds/dt = z - kappa s - gamma (f - 1),  df/dt = s,
+ *   tau0 dv/dt = f - v^(1/alpha),
+ *   tau0 dq/dt = f (1 - (1 - E0)^(1/f)) / E0 - v^(1/alpha) q / v,
+ *   BOLD = V0 (k1 (1 - q) + k2 (1 - q/v) + k3 (1 - v)),
+ * integrated by classical Runge-Kutta with the sample period as the step
+ * (time in s), sampled every tr_ms: sample m after round((m+1) tr / period)
+ * samples, n_tr = floor(n_samples period / tr_ms) samples per region.
+ * Defaults: kappa 0.65, gamma 0.41, tau0 0.98, alpha 0.32, E0 0.34, V0 0.02,
+ * k1 = 7 E0, k2 = 2, k3 = 2 E0 - 0.2, tr_ms 2000. */
+typedef struct vadx_bold_cfg {
+    double kappa, gamma, tau0, alpha, E0, V0, k1, k2, k3, tr_ms;
+} vadx_bold_cfg;
+vadx_status vadx_bold_defaults(vadx_bold_cfg *out);
+/* BOLD of device series samples [n_inst][n_samples][n] (kHz) into out
+ * (device, [n_inst][n_tr][n]); *n_tr (host) receives the sample count per
+ * region. Stream-ordered. */
+vadx_status vadx_bold_series(vadx_ctx *ctx, const float *samples, int64_t n_inst, int32_t n,
+                             int64_t n_samples, double sample_period_ms, const vadx_bold_cfg *cfg,
+                             float *out, int32_t *n_tr);
+/* BOLD of the samples of the last vadx_integrate (any mix of region counts):
+ * out (device) holds each instance's [n_tr][n] block in instance order. */
+vadx_status vadx_bold(vadx_ctx *ctx, const vadx_bold_cfg *cfg, float *out, int32_t *n_tr);
+
 /* Arithmetic of one region-step in this library's formulation, counted by
  * running the kernel's own model code with an operation-counting scalar:
  * single- and double-precision FLOPs (add, mul = 1, fma = 2, transcendental =

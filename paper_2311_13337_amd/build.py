@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvadx.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "vadx_api.cpp", "mlp.hip", "mlp_api.cpp", "select.hip",
-                                              "analysis.hip", "analysis_api.cpp")]
+                                              "analysis.hip", "analysis_api.cpp", "bold.hip")]
 HOST_SOURCES = [os.path.join(CSRC, "opcount.cpp")]   # plain C++ (g++), no device code
 ARCH = os.environ.get("VADX_OFFLOAD_ARCH", "gfx950")
 

@@ -69,6 +69,25 @@ hipError_t launch_an_final(const AnChunk &a, hipStream_t s);
 int pli_time_chunk(int n, int Na);
 int pli_passes(int n);
 
+// BOLD (bold.hip): one thread per region of the instances described by the
+// tables; out_off[i] = floats to instance i's [n_tr][n] output block; emit[m]
+// = the sample count after which BOLD sample m is taken.
+struct BoldArgs {
+    const float *samples;
+    const int64_t *samp_off;
+    const int32_t *n;
+    const int32_t *rbase;
+    const int32_t *reg_inst;
+    const int64_t *out_off;
+    const int32_t *emit;
+    int64_t n_reg, n_samples;
+    int32_t n_tr;
+    float kappa, gamma, inv_tau0, inv_alpha, inv_E0, l2_1mE0;
+    double h, V0, k1, k2, k3;
+    float *out;
+};
+hipError_t launch_bold(const BoldArgs &a, hipStream_t s);
+
 // Optional per-kernel timing of the analysis launches (HIP events on the
 // launch stream): transpose, Welch, analytic signal, PLI, Up/Down, final.
 constexpr int kAnKernels = 6;

@@ -86,6 +86,9 @@ struct vadx_ctx {
     // ranking (vadx_top_k)
     SelScratch sel;
     DevBuf<int64_t> topk_idx;
+    // BOLD tables
+    DevBuf<int64_t> b_samp, b_out;
+    DevBuf<int32_t> b_n, b_rbase, b_reg, b_emit;
     // batch
     std::vector<float> S, be, ae, v;
     std::vector<int32_t> conn_of;
@@ -1248,4 +1251,122 @@ extern "C" vadx_status vadx_set_instance_param(vadx_ctx *c, int32_t param, int64
     c->planned = false;
     c->ran = false;
     return VADX_OK;
+}
+
+// ------------------------------------------------------------------- BOLD
+extern "C" vadx_status vadx_bold_defaults(vadx_bold_cfg *p)
+{
+    if (!p) return VADX_E_ARG;
+    p->kappa = 0.65;
+    p->gamma = 0.41;
+    p->tau0 = 0.98;
+    p->alpha = 0.32;
+    p->E0 = 0.34;
+    p->V0 = 0.02;
+    p->k1 = 7.0 * 0.34;
+    p->k2 = 2.0;
+    p->k3 = 2.0 * 0.34 - 0.2;
+    p->tr_ms = 2000.0;
+    return VADX_OK;
+}
+
+static int32_t bold_count(int64_t n_samples, double period_ms, double tr_ms)
+{
+    return (int32_t)std::floor((double)n_samples * period_ms / tr_ms + 1e-9);
+}
+
+static vadx_status run_bold(vadx_ctx *c, const float *samples, const std::vector<int64_t> &off,
+                            const std::vector<int32_t> &ns, int64_t n_samples, double period_ms,
+                            const vadx_bold_cfg *p, float *out, int32_t *n_tr_out)
+{
+    if (!p || !n_tr_out) return fail(c, VADX_E_ARG, "null argument");
+    auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+    if (!(std::isfinite(p->kappa) && p->kappa >= 0.0 && pos(p->gamma) && pos(p->tau0) &&
+          pos(p->alpha) && pos(p->E0) && p->E0 < 1.0 && std::isfinite(p->V0) &&
+          std::isfinite(p->k1) && std::isfinite(p->k2) && std::isfinite(p->k3) && pos(p->tr_ms)))
+        return fail(c, VADX_E_ARG, "invalid BOLD parameters");
+    if (!pos(period_ms) || n_samples < 0) return fail(c, VADX_E_ARG, "invalid sample period or count");
+    const int32_t n_tr = bold_count(n_samples, period_ms, p->tr_ms);
+    *n_tr_out = n_tr;
+    const size_t ni = ns.size();
+    if (ni == 0 || n_tr == 0) return VADX_OK;
+    if (!samples || !out) return fail(c, VADX_E_ARG, "null samples or output");
+    std::vector<int32_t> rb(ni), emit((size_t)n_tr), reg;
+    std::vector<int64_t> oo(ni);
+    int64_t r = 0, o = 0;
+    for (size_t i = 0; i < ni; ++i) {
+        rb[i] = (int32_t)r;
+        oo[i] = o;
+        for (int k = 0; k < ns[i]; ++k) reg.push_back((int32_t)i);
+        r += ns[i];
+        o += (int64_t)n_tr * ns[i];
+    }
+    const double steps = p->tr_ms / period_ms;
+    for (int32_t m = 0; m < n_tr; ++m) emit[(size_t)m] = (int32_t)std::nearbyint((m + 1) * steps);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, c->b_samp.ensure(ni));
+    HIP_TRY(c, c->b_out.ensure(ni));
+    HIP_TRY(c, c->b_n.ensure(ni));
+    HIP_TRY(c, c->b_rbase.ensure(ni));
+    HIP_TRY(c, c->b_reg.ensure((size_t)r));
+    HIP_TRY(c, c->b_emit.ensure((size_t)n_tr));
+    HIP_TRY(c, hipMemcpyAsync(c->b_samp.p, off.data(), 8 * ni, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->b_out.p, oo.data(), 8 * ni, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->b_n.p, ns.data(), 4 * ni, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->b_rbase.p, rb.data(), 4 * ni, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->b_reg.p, reg.data(), 4 * (size_t)r, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->b_emit.p, emit.data(), 4 * (size_t)n_tr, hipMemcpyHostToDevice,
+                              c->stream));
+    BoldArgs a{};
+    a.samples = samples;
+    a.samp_off = c->b_samp.p;
+    a.n = c->b_n.p;
+    a.rbase = c->b_rbase.p;
+    a.reg_inst = c->b_reg.p;
+    a.out_off = c->b_out.p;
+    a.emit = c->b_emit.p;
+    a.n_reg = r;
+    a.n_samples = n_samples;
+    a.n_tr = n_tr;
+    a.kappa = (float)p->kappa;
+    a.gamma = (float)p->gamma;
+    a.inv_tau0 = (float)(1.0 / p->tau0);
+    a.inv_alpha = (float)(1.0 / p->alpha);
+    a.inv_E0 = (float)(1.0 / p->E0);
+    a.l2_1mE0 = (float)std::log2(1.0 - p->E0);
+    a.h = period_ms / 1000.0;
+    a.V0 = p->V0;
+    a.k1 = p->k1;
+    a.k2 = p->k2;
+    a.k3 = p->k3;
+    a.out = out;
+    HIP_TRY(c, launch_bold(a, c->stream));
+    return VADX_OK;
+}
+
+extern "C" vadx_status vadx_bold_series(vadx_ctx *c, const float *samples, int64_t n_inst,
+                                        int32_t n, int64_t n_samples, double sample_period_ms,
+                                        const vadx_bold_cfg *cfg, float *out, int32_t *n_tr)
+{
+    if (!c) return VADX_E_ARG;
+    if (n_inst < 0 || n < 1 || n > 512) return fail(c, VADX_E_ARG, "bad sizes");
+    std::vector<int64_t> off((size_t)n_inst);
+    std::vector<int32_t> ns((size_t)n_inst, n);
+    for (int64_t i = 0; i < n_inst; ++i) off[(size_t)i] = i * n_samples * n;
+    return run_bold(c, samples, off, ns, n_samples, sample_period_ms, cfg, out, n_tr);
+}
+
+extern "C" vadx_status vadx_bold(vadx_ctx *c, const vadx_bold_cfg *cfg, float *out, int32_t *n_tr)
+{
+    if (!c) return VADX_E_ARG;
+    if (!c->ran) return fail(c, VADX_E_STATE, "no samples: call vadx_integrate first");
+    const size_t ni = c->h_inst.size();
+    std::vector<int64_t> off(ni);
+    std::vector<int32_t> ns(ni);
+    for (size_t i = 0; i < ni; ++i) {
+        off[i] = c->h_inst[i].samp_off;
+        ns[i] = c->h_inst[i].n;
+    }
+    const double period = (double)c->plan_run.tavg_steps * c->plan_run.dt_ms;
+    return run_bold(c, (const float *)c->ws, off, ns, c->n_samples, period, cfg, out, n_tr);
 }

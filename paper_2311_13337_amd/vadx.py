@@ -34,7 +34,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
            "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze",
            "vadx_analysis_kernel_time", "vadx_set_reference_fc", "vadx_top_k",
-           "vadx_set_instance_param")
+           "vadx_set_instance_param", "vadx_bold_defaults", "vadx_bold_series", "vadx_bold")
 INSTANCE_PARAMS = {"w_noise": 0, "tau_w_e": 1, "cF_ee": 2, "cF_ei": 3, "cF_ie": 4, "cF_ii": 5}
 ANALYSIS_KERNELS = ("an_transpose_kernel", "an_welch_kernel", "an_hilbert_kernel", "an_pli_kernel",
                     "an_ud_kernel", "an_final_kernel")
@@ -81,6 +81,11 @@ class vadx_analysis(C.Structure):
         ("reserved", C.c_float), ("psd_peak_bin", C.c_int32), ("psd_fit_bins", C.c_int32),
         ("ud_up_count", C.c_int32), ("ud_down_count", C.c_int32),
         ("ud_up_samples", C.c_int64), ("ud_down_samples", C.c_int64)]
+
+
+class vadx_bold_cfg(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("kappa", "gamma", "tau0", "alpha", "E0", "V0", "k1",
+                                          "k2", "k3", "tr_ms")]
 
 
 class vadx_stats(C.Structure):
@@ -158,6 +163,10 @@ def lib():
             "vadx_set_reference_fc": (st, [vp, C.c_int32, vp]),
             "vadx_top_k": (st, [vp, vp, C.c_int64, C.c_int32, vp, vp]),
             "vadx_set_instance_param": (st, [vp, C.c_int32, C.c_int64, vp]),
+            "vadx_bold_defaults": (st, [P(vadx_bold_cfg)]),
+            "vadx_bold_series": (st, [vp, vp, C.c_int64, C.c_int32, C.c_int64, C.c_double,
+                                      P(vadx_bold_cfg), vp, P(C.c_int32)]),
+            "vadx_bold": (st, [vp, P(vadx_bold_cfg), vp, P(C.c_int32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -354,6 +363,28 @@ class Context:
                                      C.c_void_p(idx.data_ptr()), C.c_void_p(val.data_ptr())))
         return idx[:k], val[:k]
 
+    def vadx_bold_series(self, samples, n_samples: int, n: int, period_ms: float,
+                         cfg: "vadx_bold_cfg" = None):
+        """samples: device tensor [n_inst][n_samples][n]; returns the device
+        tensor [n_inst][n_tr][n] of BOLD samples."""
+        import torch
+        cfg = cfg or vadx_bold_defaults()
+        n_inst = samples.shape[0]
+        n_tr = int(np.floor(n_samples * period_ms / cfg.tr_ms + 1e-9))
+        out = torch.empty((n_inst, max(n_tr, 0), n), dtype=torch.float32, device=samples.device)
+        got = C.c_int32()
+        self._check(lib().vadx_bold_series(self.h, C.c_void_p(samples.data_ptr()), n_inst, n,
+                                           n_samples, period_ms, C.byref(cfg),
+                                           C.c_void_p(out.data_ptr()), C.byref(got)))
+        assert got.value == n_tr
+        return out
+
+    def vadx_bold(self, cfg: "vadx_bold_cfg", out):
+        got = C.c_int32()
+        self._check(lib().vadx_bold(self.h, C.byref(cfg), C.c_void_p(out.data_ptr()),
+                                    C.byref(got)))
+        return got.value
+
     def vadx_analyze(self, cfg: "vadx_analysis_cfg", ws, out):
         self._check(lib().vadx_analyze(self.h, C.byref(cfg), C.c_void_p(ws.data_ptr()),
                                        ws.numel() * ws.element_size(), C.c_void_p(out.data_ptr())))
@@ -365,6 +396,14 @@ def analysis_kernel_time(ctx: "Context"):
     ms = np.zeros(6, np.float64)
     ctx._check(lib().vadx_analysis_kernel_time(ctx.h, _ptr(n), _ptr(ms)))
     return {k: (int(a), float(b)) for k, a, b in zip(ANALYSIS_KERNELS, n, ms)}
+
+
+def vadx_bold_defaults() -> vadx_bold_cfg:
+    c = vadx_bold_cfg()
+    s = lib().vadx_bold_defaults(C.byref(c))
+    if s != VADX_OK:
+        raise VadxError(s, "BOLD defaults")
+    return c
 
 
 def vadx_analysis_defaults() -> vadx_analysis_cfg:

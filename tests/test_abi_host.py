@@ -73,3 +73,10 @@ def test_analysis_workspace_query_and_defaults():
         setattr(bad, field, value)
         with pytest.raises(vadx.VadxError):
             vadx.vadx_analysis_ws_bytes(40000, 68, 68, bad)
+
+
+def test_bold_defaults_match_oracle():
+    from oracle import analysis as oa
+    c = vadx.vadx_bold_defaults()
+    for k, v in oa.BOLD_DEFAULTS.items():
+        assert getattr(c, k) == pytest.approx(v, rel=1e-15), k

@@ -220,3 +220,54 @@ def test_analysis_full_size_sampled():
     assert np.array_equal(pli_h[16:].reshape(255, 16, n, n), np.broadcast_to(pli_h[:16], (255, 16, n, n)))
     for j in range(16):
         _check(g[j], psd_h[j], pli_h[j], _oracle(base[j], 1.0, cfg), ("full", j))
+
+
+@pytest.mark.parametrize("n_inst,n,ns,period,tr", [(2, 68, 9000, 1.0, 2000.0), (2, 5, 3000, 1.0, 720.0),
+                                                   (1, 3, 500, 2.0, 250.0), (1, 4, 100, 1.0, 2000.0)])
+def test_bold_against_oracle(n_inst, n, ns, period, tr):
+    """BOLD (Balloon-Windkessel) against the FP64 oracle on seeded synthetic
+    rate series: the derivatives are single precision, the state double, so the
+    signal agrees to |dy| <= 1e-4 max|y| + 1e-8 (a derivative error of ~1e-7
+    relative per evaluation, damped by the haemodynamic time constants)."""
+    import torch
+    from oracle import analysis as oa
+    print(f"[bold] n_inst={n_inst} n={n} ns={ns} period={period} tr={tr}", flush=True)
+    S = inputs.synthetic_rate_series(n_inst, n, ns, seed=51, period_ms=period)
+    cfg = vadx.vadx_bold_defaults()
+    cfg.tr_ms = tr
+    ctx = vadx.Context(0)
+    y = ctx.vadx_bold_series(torch.from_numpy(S).cuda(), ns, n, period, cfg).cpu().numpy()
+    for i in range(n_inst):
+        o = oa.bold_series(S[i], period, tr_ms=tr)
+        assert y[i].shape == o.shape
+        if o.size == 0:
+            continue
+        err = np.abs(y[i].astype(np.float64) - o).max()
+        print(f"[bold] instance {i}: max|dy| {err:.3g}, max|y| {np.abs(o).max():.3g}", flush=True)
+        assert err <= 1e-4 * np.abs(o).max() + 1e-8
+
+
+def test_bold_after_integration_matches_series():
+    import torch
+    sw = vadx.Sweep(0)
+    sw.add_connectome(inputs.synthetic_connectome(68))
+    b = inputs.grid_small()
+    sw.set_batch(b)
+    sw.plan(vadx.make_run(inputs.RunConfig(n_steps=30000, transient_steps=2000)))
+    sw.integrate()
+    sw.sync()
+    n, ns = sw.ctx.vadx_instance_shape(0)
+    cfg = vadx.vadx_bold_defaults()
+    cfg.tr_ms = 500.0
+    n_tr = int(ns * 1.0 // 500.0)
+    out = torch.empty((len(b.S), n_tr, n), dtype=torch.float32, device="cuda")
+    assert sw.ctx.vadx_bold(cfg, out) == n_tr
+    S = torch.from_numpy(np.stack([sw.ctx.vadx_read_samples(i) for i in range(len(b.S))])).cuda()
+    y = sw.ctx.vadx_bold_series(S, ns, n, 1.0, cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(out, y)
+    assert torch.isfinite(out).all()
+    bad = vadx.vadx_bold_defaults()
+    bad.E0 = 1.5
+    with pytest.raises(vadx.VadxError):
+        sw.ctx.vadx_bold(bad, out)
