@@ -386,6 +386,7 @@ static hipError_t launch_integrate_v(const IntegrateArgs &a, int n_groups, int b
     case 4: return launch_integrate_b<4, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     case 8: return launch_integrate_b<8, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     case 16: return launch_integrate_b<16, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 24: return launch_integrate_b<24, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     case 32: return launch_integrate_b<32, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
     default: return hipErrorInvalidValue;
     }
@@ -435,6 +436,7 @@ template <int OCC> static int resident(int block, int block_threads)
     case 4: return resident_b<4, OCC>(block_threads);
     case 8: return resident_b<8, OCC>(block_threads);
     case 16: return resident_b<16, OCC>(block_threads);
+    case 24: return resident_b<24, OCC>(block_threads);
     case 32: return resident_b<32, OCC>(block_threads);
     default: return 0;
     }

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <numeric>
 #include <sstream>
 #include <string>
 #include <utility>
@@ -100,6 +101,7 @@ struct vadx_ctx {
     bool planned = false;
     vadx_run plan_run{};
     int block = 1;                       // longest block length of the plan
+    int block_lcm = 1;                   // least common multiple of the plan's block lengths
     int wg_threads = 64;                 // widest workgroup of the plan
     std::vector<BlockClass> classes;     // groups of one block length, launched together
     std::vector<InstDev> h_inst;
@@ -451,12 +453,17 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         dmax[i] = hc.nnz ? host_delay(hc.len_max, c->v[i], r->dt_ms) : 1;
         if (dmax[i] >= (1 << 20) - kMaxBlock - 2)
             return fail(c, VADX_E_UNSUPPORTED, "delay of %lld steps too long", (long long)dmax[i]);
+        // the longest of 1, 2, 4, 8, 16, 24, 32 steps within the bound
         int B = 1;
-        while (B * 2 <= kMaxBlock && B * 2 <= dm + 1) B *= 2;
+        for (int cand : {2, 4, 8, 16, 24, 32})
+            if (cand <= kMaxBlock && cand <= dm + 1) B = cand;
         blk[i] = B;
         bmax = std::max(bmax, B);
     }
     c->block = bmax;
+    // launch and item lengths are multiples of every block length present
+    c->block_lcm = 1;
+    for (int64_t i = 0; i < ni; ++i) c->block_lcm = std::lcm(c->block_lcm, blk[i]);
     // delay tables: one per distinct (connectome, speed)
     std::map<std::pair<int32_t, uint32_t>, int32_t> tab;
     c->h_tables.clear();
@@ -629,14 +636,15 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     a.integrator = r->integrator;
     // default launch length: the whole run for the persistent queue (its only
     // tail is then the end of the run), 10000 steps for one-workgroup-per-group.
-    // Launch and item lengths are multiples of every block length (powers of 2
-    // up to the plan's longest).
+    // Launch and item lengths are multiples of every block length of the plan
+    // (their least common multiple), so blocks stay whole inside a run.
     int64_t chunk = r->chunk_steps > 0 ? r->chunk_steps
                                        : (c->launch_mode == 0 ? std::max<int64_t>(r->n_steps, 1) : 10000);
     // (a launch that reaches the end of the run may end on a partial block)
+    const int64_t bl = c->block_lcm;
     chunk = chunk >= r->n_steps ? std::max<int64_t>(r->n_steps, 1)
-                                : std::max<int64_t>(chunk / c->block, 1) * c->block;
-    const int64_t item_steps = std::max<int64_t>(c->item_steps / c->block, 1) * c->block;
+                                : std::max<int64_t>(chunk / bl, 1) * bl;
+    const int64_t item_steps = std::max<int64_t>(c->item_steps / bl, 1) * bl;
     if (c->launch_mode == 0) {
         uint32_t *status = (uint32_t *)((char *)ws + c->off_queue) + 1;
         HIP_TRY(c, launch_fill_u32(status, 1, 0u, st));

@@ -332,8 +332,8 @@ def test_launch_shapes_are_bit_identical():
 
 
 def test_block_length_classes_are_bit_identical():
-    """Each instance steps in blocks of up to d_min + 1 steps of its own (8, 16
-    or 32 here, one launch per block length); the coupling values do not depend
+    """Each instance steps in blocks of up to d_min + 1 steps of its own (8, 16,
+    24 or 32 here, one launch per block length); the coupling values do not depend
     on the block length, so an instance run alone -- its own block class --
     matches the same instance in the mixed batch bit for bit."""
     conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
