@@ -6,6 +6,7 @@ the feature, which is harmless.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -28,35 +29,39 @@ def hipcc() -> str:
     return h
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source and links libvadx.so (always rebuilds)."""
-    objs = []
+def _compile(cmd: list, src: str, what: str) -> str:
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"{what} failed on {src}")
+    return r.stderr
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compiles every source (in parallel, `jobs` processes, default one per
+    source up to the host's cores) and links libvadx.so (always rebuilds)."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    work = []
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
-        cmd = [hipcc(), *common, "-c", src, "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [hipcc(), *common, "-x", "hip", "-c", src, "-o", obj]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
-        if verbose:
-            sys.stderr.write(r.stderr)
-        objs.append(obj)
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        work.append(([hipcc(), *common, *lang, "-c", src, "-o", obj], src, "hipcc", obj))
     for src in HOST_SOURCES:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
-        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-               "-c", src, "-o", obj]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"g++ failed on {src}")
-        objs.append(obj)
+        work.append((["g++", "-O2", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                      "-c", src, "-o", obj], src, "g++", obj))
+    n = jobs or max(1, min(len(work), os.cpu_count() or 1, 16))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=n) as pool:
+        futs = [pool.submit(_compile, cmd, src, what) for cmd, src, what, _ in work]
+        for f in futs:
+            log = f.result()
+            if verbose:
+                sys.stderr.write(log)
+    objs = [obj for *_, obj in work]
     tmp = LIB + ".tmp"
     r = subprocess.run([hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs],
                        capture_output=True, text=True)
