@@ -115,6 +115,10 @@ __device__ __forceinline__ void normals4(uint32_t seed, uint32_t id, uint32_t q,
 }
 
 // ------------------------------------------------------------------ integrate
+// Edges whose delayed histories a full block loads in one round of the
+// coupling gather: about 96 floats in flight per lane.
+template <int B> constexpr int kGatherEdges = B >= 96 ? 1 : (96 / B > 8 ? 8 : 96 / B);
+
 // Integrates the instances of group g over steps [n_begin, n_end). All
 // threads of the workgroup call it with the same (wave-uniform) arguments: it
 // contains workgroup barriers.
@@ -197,15 +201,38 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
 #pragma unroll
             for (int b = 0; b < B; ++b) cb[b] = 0.f;
             if (nb == B) {
-                for (int e = row_b; e < row_e; ++e) {
-                    const int32_t pk = prow[e];
-                    const int j = pk >> 20, d = pk & 0xFFFFF;
-                    const float w = wrow[e];
-                    int s0 = nm - d;
-                    s0 += (s0 < 0) ? D : 0;
-                    const float *h = ring + (int64_t)j * Dp + s0;
+                // kGatherEdges edges per round: their index and history loads
+                // are all in flight before the first multiply-add, so a row
+                // costs a few memory round trips instead of two per edge. The
+                // sums still run over the edges in row order. A round past the
+                // row's end reloads the row's first edge and adds nothing.
+                constexpr int U = kGatherEdges<B>;
+                for (int e0 = row_b; e0 < row_e; e0 += U) {
+                    const float *h[U];
+                    float w[U];
+                    bool ok[U];
 #pragma unroll
-                    for (int b = 0; b < B; ++b) cb[b] = fmaf(w, h[b], cb[b]);
+                    for (int u = 0; u < U; ++u) {
+                        ok[u] = e0 + u < row_e;
+                        const int e = ok[u] ? e0 + u : row_b;
+                        const int32_t pk = prow[e];
+                        const int j = pk >> 20, d = pk & 0xFFFFF;
+                        w[u] = wrow[e];
+                        int s0 = nm - d;
+                        s0 += (s0 < 0) ? D : 0;
+                        h[u] = ring + (int64_t)j * Dp + s0;
+                    }
+                    float hv[U][B];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int b = 0; b < B; ++b) hv[u][b] = h[u][b];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (ok[u]) {
+#pragma unroll
+                            for (int b = 0; b < B; ++b) cb[b] = fmaf(w[u], hv[u][b], cb[b]);
+                        }
                 }
             } else {
                 for (int e = row_b; e < row_e; ++e) {
