@@ -106,7 +106,7 @@ hipError_t launch_delays(int n_tables, const DelayTableDev *tables, const ConnDe
 // q == nullptr: one workgroup per group over [a.n_begin, a.n_end); otherwise the
 // persistent kernel with `grid` workgroups draining the queue.
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
-// occ: waves per SIMD of the persistent kernel's register budget (2 or 4)
+// occ: waves per SIMD of the persistent kernel's register budget (2 or 3)
 hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
                             const QueueArgs *q, int grid, int occ, hipStream_t s);
 int persistent_blocks_per_cu(int block, int block_threads, int occ);

@@ -116,8 +116,11 @@ __device__ __forceinline__ void normals4(uint32_t seed, uint32_t id, uint32_t q,
 
 // ------------------------------------------------------------------ integrate
 // Edges whose delayed histories a full block loads in one round of the
-// coupling gather: about 96 floats in flight per lane.
-template <int B> constexpr int kGatherEdges = B >= 96 ? 1 : (96 / B > 8 ? 8 : 96 / B);
+// coupling gather: about 96 floats in flight per lane for blocks of 24 and 32
+// steps, 64 for shorter ones (measured: 6 edges of 16 steps ran slower than 4).
+template <int B> constexpr int kGatherFloats = B > 16 ? 96 : 64;
+template <int B> constexpr int kGatherEdges =
+    B >= kGatherFloats<B> ? 1 : (kGatherFloats<B> / B > 8 ? 8 : kGatherFloats<B> / B);
 
 // Integrates the instances of group g over steps [n_begin, n_end). All
 // threads of the workgroup call it with the same (wave-uniform) arguments: it

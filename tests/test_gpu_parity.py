@@ -255,6 +255,34 @@ def test_ragged_groups_and_short_delays(oracle):
                                        rtol=1e-4, atol=1e-9)
 
 
+def test_isolated_and_dense_rows(oracle):
+    """Rows with no edges (an isolated region), one edge, and 27 edges (more
+    than a 24-step block's gather rounds of four edges cover evenly), at
+    v = 5 m/s (shortest delay 27 steps: 24-step blocks): traced against the
+    oracle."""
+    base = inputs.synthetic_connectome(30, seed=11)
+    W, T = base.weights.copy(), base.tract_mm.copy()
+    W[0, :] = W[:, 0] = 0.0                      # region 0 isolated
+    W[2, :] = W[:, 2] = 0.0
+    W[2, 3] = W[3, 2] = 0.05                     # region 2: one edge
+    for j in range(3, 30):                       # region 1: 27 edges
+        W[1, j] = W[j, 1] = 0.02 + 0.001 * j
+    W[1, 0] = W[0, 1] = W[1, 2] = W[2, 1] = 0.0
+    conn = inputs.Connectome(weights=W, tract_mm=T)
+    rng = np.random.default_rng(4)
+    batch = inputs._batch(rng.uniform(0.05, 0.2, 5), rng.uniform(0, 60, 5), rng.uniform(0, 4, 5),
+                          [5.0] * 5)
+    cfg = inputs.RunConfig(n_steps=480, transient_steps=100, n_trace_steps=480, seed=6)
+    print("[parity] isolated / one-edge / 27-edge rows, 5 instances", flush=True)
+    sw = run_gpu("literature-B", [conn], batch, cfg, trace=range(5))
+    assert sw.ctx.vadx_launch_info()["steps_per_block"] == 24
+    ref = run_oracle(oracle, "literature-B", conn, batch, cfg)
+    pert = run_oracle(oracle, "literature-B", conn, batch, cfg, perturb=True)
+    for i in range(5):
+        g = sw.ctx.vadx_read_trace(i, i, 480).astype(np.float64)
+        check_trace(g, ref["trace"][i], pert["trace"][i], f"isolated/dense rows instance {i}")
+
+
 def test_mixed_region_counts_one_launch(oracle):
     """68-, 84- and 200-region networks with different speeds in one launch."""
     conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
