@@ -95,6 +95,7 @@ struct FcArgs {
     uint32_t *flags;
     int64_t n_samples;
     double min_var;             // silence threshold on a region's variance
+    int32_t max_n;              // most regions of an instance (sizes the LDS)
 };
 
 // Launchers (return hipError_t of the launch).

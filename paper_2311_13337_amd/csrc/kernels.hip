@@ -480,12 +480,20 @@ int persistent_blocks_per_cu(int block, int block_threads, int occ)
 
 // ------------------------------------------------------------------ FC and statistics
 // One workgroup per instance. Rates are shifted by the first sample of each
-// region (exact in FP64), then: per-region sums and sums of squares; the Gram
-// matrix of the shifted samples over 4x4 tiles of the upper triangle, staged
-// through LDS in chunks of samples; covariance, Pearson FC, and the statistics.
+// region (exact in FP64) and staged through LDS in FP64, in chunks of
+// samples; from them, per-region sums and sums of squares and the Gram matrix
+// over 4x4 tiles of the upper triangle; then covariance, Pearson FC, and the
+// statistics.
 constexpr int kFcThreads = 256;
-constexpr int kFcLdsFloats = 8192;
+constexpr int kFcStageDoubles = 4096;    // shifted samples staged per chunk (32 KB)
 constexpr int kFcRegionsPerThread = 4;   // regions per thread in the moment sums (n <= 1024)
+
+// Dynamic LDS of fc_stats_kernel for instances of up to max_n regions: the
+// staged samples, shift / mean / variance per region, a reduction buffer.
+size_t fc_lds_bytes(int max_n)
+{
+    return sizeof(double) * ((size_t)kFcStageDoubles + 3 * (size_t)max_n + kFcThreads);
+}
 
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
@@ -503,9 +511,10 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 
 __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
 {
-    __shared__ float xs[kFcLdsFloats];
-    __shared__ double shift[1024], mean[1024], var[1024];
-    __shared__ double red[kFcThreads];
+    extern __shared__ __align__(16) double fcl[];   // fc_lds_bytes(a.max_n)
+    double *xs = fcl;                                // [chunk][npad] shifted samples
+    double *shift = xs + kFcStageDoubles, *mean = shift + a.max_n, *var = mean + a.max_n;
+    double *red = var + a.max_n;
     const int64_t inst = blockIdx.x;
     const InstDev I = a.inst[inst];
     const ConnDev C = a.conns[I.conn];
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
 
     const int nT = (n + 3) / 4, npad = nT * 4;
     const int ntiles = nT * (nT + 1) / 2;
-    const int chunk = kFcLdsFloats / npad;
+    const int chunk = kFcStageDoubles / npad;
     double s_f = 0, s_f2 = 0, s_w = 0, s_w2 = 0, s_fw = 0, s_cov = 0;
     double s_r = 0, s_r2 = 0, s_fr = 0;           // reference FC (fitness)
     // per-region sums of the shifted samples and of their squares, gathered
@@ -549,7 +558,7 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
             __syncthreads();
             for (int i = tid; i < cn * npad; i += kFcThreads) {
                 const int s = i / npad, k = i - s * npad;
-                xs[i] = k < n ? x[(s0 + s) * n + k] : 0.f;
+                xs[i] = k < n ? (double)x[(s0 + s) * n + k] - shift[k] : 0.0;
             }
             __syncthreads();
             if (t0 == 0) {
@@ -557,9 +566,8 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
                 for (int q = 0; q < kFcRegionsPerThread; ++q) {
                     const int k = tid + q * kFcThreads;
                     if (k < n) {
-                        const double sh = shift[k];
                         for (int s = 0; s < cn; ++s) {
-                            const double v = (double)xs[s * npad + k] - sh;
+                            const double v = xs[s * npad + k];
                             m1[q] += v;
                             m2[q] = fma(v, v, m2[q]);
                         }
@@ -567,20 +575,13 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
                 }
             }
             if (t < ntiles) {
-                double sa[4], sb[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int ka = tr * 4 + i, kb = tcol * 4 + i;
-                    sa[i] = ka < n ? shift[ka] : 0.0;
-                    sb[i] = kb < n ? shift[kb] : 0.0;
-                }
                 for (int s = 0; s < cn; ++s) {
-                    const float *row = xs + s * npad;
+                    const double *row = xs + s * npad;
                     double va[4], vb[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        va[i] = (double)row[tr * 4 + i] - sa[i];
-                        vb[i] = (double)row[tcol * 4 + i] - sb[i];
+                        va[i] = row[tr * 4 + i];
+                        vb[i] = row[tcol * 4 + i];
                     }
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
@@ -717,7 +718,14 @@ hipError_t launch_rank_sort(const float *val, const int64_t *idx, int32_t k, int
 hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s)
 {
     if (n_inst == 0) return hipSuccess;
-    hipLaunchKernelGGL(fc_stats_kernel, dim3((unsigned)n_inst), dim3(kFcThreads), 0, s, a);
+    if (a.max_n < 1 || a.max_n > 1024) return hipErrorInvalidValue;
+    const size_t lds = fc_lds_bytes(a.max_n);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fc_stats_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fc_stats_kernel, dim3((unsigned)n_inst), dim3(kFcThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -690,6 +690,8 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     f.flags = flags;
     f.n_samples = c->n_samples;
     f.min_var = r->fc_min_std * r->fc_min_std;
+    f.max_n = 1;
+    for (const HostConn &hc : c->conns) f.max_n = std::max(f.max_n, hc.n);
     hipEvent_t stop = nullptr;
     if (timed) { vadx_status e = record(c, c->ev_fc, &stop); if (e) return e; }
     HIP_TRY(c, launch_fc_stats(f, ni, st));
