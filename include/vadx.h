@@ -271,7 +271,7 @@ vadx_status vadx_kernel_time(vadx_ctx *ctx, int64_t *n_integrate_launches, doubl
  * mapping a sweep point (S, b_e, a_e, v) to the six statistics of
  * vadx_read_stats, trained on the GPU by this library's kernels so a dense grid
  * can be screened before simulating (the learning-guided exploration the
- * paper's discussion proposes; the plain simulation stays the judge).
+ * paper's discussion proposes; the plain simulation stays the reference).
  * Inputs are min-max scaled to [-1, 1] with cfg.x_lo / x_hi; targets are
  * z-scored with the network's target normalisation. Matrix products use
  * bfloat16 operands with FP32 accumulation (MFMA for the 128 x 128 products);

@@ -15,7 +15,7 @@ The plain method simulates every point of a dense grid. The guided sweep
      that would stay unrefined with an FC error above the bound, and refines
      further down the score ranking until that estimate is below the target,
   6. keeps the predictions elsewhere.
-The plain simulation stays the judge: the error of the guided result is
+The plain simulation stays the reference: the error of the guided result is
 measured against plain runs of a random sample of grid points (bit-identical
 to the full plain sweep at those points), and the plain sweep's time is the
 measured per-instance time of the same simulations times the grid size.

@@ -117,7 +117,7 @@ def fc_verdict(label, fc, st, ens, q):
     if d.mean() > 2 * d_ens + 0.01:
         return False, f"{label}: mean|dFC| {d.mean():.3g} vs {d_ens:.3g}"
     # a chaotic run's statistics are random over single-precision-sized
-    # perturbations: the GPU run is one more draw, judged by a prediction
+    # perturbations: the GPU run is one more draw, checked against a prediction
     # interval of the ensemble (5 standard deviations: t with 11 degrees of
     # freedom at the 99.95 % level, times sqrt(1 + 1/12))
     mu, sd = ost.mean(0), ost.std(0, ddof=1)
@@ -523,7 +523,7 @@ def test_fitness_against_reference_fc_and_ranking(oracle):
     """Fitness (Pearson of FC with a reference FC over k < l) and the grid
     search's ranking. The reference is the oracle's FC of one predictable small-grid
     instance (the paper's external FC file is not available); every GPU
-    instance's fc_fit is judged like the FC statistics against the oracle
+    instance's fc_fit is checked like the FC statistics against the oracle
     ensemble, and the ranking puts that instance first."""
     from oracle import analysis as oa
     conn = inputs.synthetic_connectome(68)

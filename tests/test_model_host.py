@@ -5,7 +5,7 @@ tests' job; here the bound is what FP32 evaluation of the same quantities
 allows. Errors of the jet components are measured against the size of the
 terms they enter (F, and the first- and second-order terms of F's Taylor
 expansion over the inputs (xe, xi): F_a xe, F_ab xe xi, ...), so that a
-derivative passing through zero is judged by the scale it matters at. FP32
+derivative passing through zero is measured on the scale it matters at. FP32
 evaluation of erfc far in its tail multiplies the input rounding by about
 2 Z^2 (Z up to ~5 here): median errors of a few 1e-8, 5e-5 at the 99th
 percentile and 2e-4 at worst are the bound.
