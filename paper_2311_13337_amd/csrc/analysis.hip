@@ -483,6 +483,8 @@ hipError_t launch_an_pli(const AnChunk &a, int max_n, hipStream_t s)
 // of one instance read consecutive addresses). Thresholds are formed in single
 // precision without contraction, so they equal those of any other
 // single-precision evaluation of the same expressions.
+constexpr int kUdUnroll = 16;
+
 __global__ __launch_bounds__(kUdThreads) void an_ud_kernel(AnChunk a)
 {
 #pragma clang fp contract(off)
@@ -492,11 +494,18 @@ __global__ __launch_bounds__(kUdThreads) void an_ud_kernel(AnChunk a)
     const int n = a.n[i];
     const int k = g - a.rbase[i];
     const float *x = a.samples + a.samp_off[i] + (a.n_samples - a.Na) * (int64_t)n + k;
+    // both passes load kUdUnroll samples before using any (more loads in flight
+    // per thread; the window length is a power of two >= 16)
     float mn = x[0], mx = x[0];
-    for (int t = 1; t < a.Na; ++t) {
-        const float v = x[(int64_t)t * n];
-        mn = fminf(mn, v);
-        mx = fmaxf(mx, v);
+    for (int t0 = 0; t0 < a.Na; t0 += kUdUnroll) {
+        float v[kUdUnroll];
+#pragma unroll
+        for (int u = 0; u < kUdUnroll; ++u) v[u] = x[(int64_t)(t0 + u) * n];
+#pragma unroll
+        for (int u = 0; u < kUdUnroll; ++u) {
+            mn = fminf(mn, v[u]);
+            mx = fmaxf(mx, v[u]);
+        }
     }
     int su = 0, nu = 0, sd = 0, nd = 0;
     const float r = mx - mn;
@@ -507,17 +516,24 @@ __global__ __launch_bounds__(kUdThreads) void an_ud_kernel(AnChunk a)
         const float up = centre + h, dn = centre - h;
         int state = 0, entered = 0;
         bool real_entry = false;
-        for (int t = 0; t < a.Na; ++t) {
-            const float v = x[(int64_t)t * n];
-            const int c = v > up ? 1 : (v < dn ? -1 : state);
-            if (c != state) {
-                if (real_entry) {
-                    if (state > 0) { su += t - entered; ++nu; }
-                    else { sd += t - entered; ++nd; }
+        for (int t0 = 0; t0 < a.Na; t0 += kUdUnroll) {
+            float vv[kUdUnroll];
+#pragma unroll
+            for (int u = 0; u < kUdUnroll; ++u) vv[u] = x[(int64_t)(t0 + u) * n];
+#pragma unroll
+            for (int u = 0; u < kUdUnroll; ++u) {
+                const int t = t0 + u;
+                const float v = vv[u];
+                const int c = v > up ? 1 : (v < dn ? -1 : state);
+                if (c != state) {
+                    if (real_entry) {
+                        if (state > 0) { su += t - entered; ++nu; }
+                        else { sd += t - entered; ++nd; }
+                    }
+                    real_entry = state != 0;
+                    state = c;
+                    entered = t;
                 }
-                real_entry = state != 0;
-                state = c;
-                entered = t;
             }
         }
     }
