@@ -168,6 +168,7 @@ def perturbed_runs(conn, batch, cfg, i, key, k=4):
             Ss += [up, max(dn, np.float32(0))]
         sub = batch.subset([i] * len(Ss))
         sub.S[:] = np.array(Ss, np.float32)
+        sub.conn[:] = 0                      # the one connectome of this run
         sw = vadx.Sweep(0, gpu_model("literature-B"))
         sw.add_connectome(conn)
         sw.set_batch(sub, noise_keys=[key] * len(Ss))
@@ -233,6 +234,38 @@ def test_long_run_uniform_sweep_sampled(oracle):
         check_fc(f"uniform sweep instance {i}", sw.ctx.vadx_read_fc(i), st[i], ens, q,
                  perturbed_runs(conn, batch, cfg, i, i))
     assert np.all(np.isfinite([st[i]["fc_mean"] for i in range(len(batch))]))
+
+
+def test_long_run_uneven_batch_sampled(oracle):
+    """The uneven batch the benchmark times (8192 instances of 68, 84 and 200
+    regions, v ~ U(1, 10) m/s, 5 s; one persistent launch per block length):
+    FC and statistics of one active instance per region count, each in a
+    different block-length class, against the oracle run one by one (ensemble
+    members in parallel host threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
+    batch = inputs.grid_uneven(8192, seed=3)
+    cfg = inputs.RUN_UNEVEN
+    # active (non-silent) instances, found with the oracle: 68 regions at 1.66 m/s
+    # (32-step blocks), 84 regions at 5.75 m/s (16), 200 regions at 9.34 m/s (8);
+    # all three are chaotic over 5 s, so the ensemble's prediction interval applies
+    pick = [324, 483, 4]
+    assert [int(batch.conn[i]) for i in pick] == [0, 1, 2]
+    print("[parity] uneven batch 8192 x 50000 steps on the GPU; sampled", pick, flush=True)
+    sw = run_gpu("literature-B", conns, batch, cfg)
+    st = sw.stats()
+    assert np.all(np.isfinite([st[i]["fc_mean"] for i in range(len(batch))]))
+    for i in pick:
+        c = int(batch.conn[i])
+        sub = batch.subset([i])
+        def member(r):
+            return run_oracle(oracle, "literature-B", conns[c], sub, cfg, inst_ids=[i], rel=r,
+                              want_samples=False)
+        ens = [member(ENSEMBLE[0])]
+        with ThreadPoolExecutor(max_workers=min(len(ENSEMBLE), os.cpu_count() or 1)) as ex:
+            ens += list(ex.map(member, ENSEMBLE[1:]))
+        check_fc(f"uneven batch instance {i} ({conns[c].n} regions, v {batch.v[i]:.2f})",
+                 sw.ctx.vadx_read_fc(i), st[i], ens, 0, perturbed_runs(conns[c], batch, cfg, i, i))
 
 
 def test_ragged_groups_and_short_delays(oracle):
