@@ -86,6 +86,8 @@ def lib():
         L.oracle_step_region.argtypes = [P(Model), C.c_int, C.c_double, dp, C.c_double, C.c_double,
                                          C.c_double, C.c_double]
         L.oracle_step_region.restype = C.c_uint32
+        L.oracle_project.argtypes = [P(Model), dp]
+        L.oracle_project.restype = C.c_uint32
         vp = C.c_void_p
         L.oracle_run.argtypes = [P(Model), P(RunCfg), C.c_int, dp, dp, C.c_int64, fp, fp, fp, fp,
                                  up, vp, vp, dp, vp, vp, vp, vp, up, C.c_int]
@@ -123,6 +125,14 @@ def drift(m: Model, X, c: float, b_e: float, a_e: float) -> np.ndarray:
 def step_region(m: Model, X, c, b_e, a_e, z, dt=0.1, integrator=0):
     X = np.array(X, np.float64)
     flags = lib().oracle_step_region(C.byref(m), integrator, dt, X, c, b_e, a_e, z)
+    return X, flags
+
+
+def project(m: Model, X):
+    """The admissible-state projection applied after each stage; returns
+    (projected state, flag bits)."""
+    X = np.array(X, np.float64)
+    flags = lib().oracle_project(C.byref(m), X)
     return X, flags
 
 

@@ -479,6 +479,10 @@ static uint32_t clamp_rates(const or_model *m, double *X)
     return hit;
 }
 
+/* Python entry: the admissible-state projection on its own (X: 8 states,
+   modified in place); returns FLAG_CLAMP when a value moved. */
+uint32_t oracle_project(const or_model *m, double *X) { return clamp_rates(m, X); }
+
 /* integrator: 0 = stochastic Heun, 1 = Euler-Maruyama. Returns flag bits. */
 uint32_t oracle_step_region(const or_model *m, int integrator, double dt, double *X, double c,
                             double b_e, double a_e, double z)
