@@ -55,6 +55,15 @@ def parse():
     p.add_argument("--analysis-cpu-instances", type=int, default=8)
     p.add_argument("--no-guided", action="store_true",
                    help="skip the surrogate-guided sweep of the 32^4 grid (about a minute and a half)")
+    p.add_argument("--no-uneven", action="store_true",
+                   help="skip the uneven-batch object (8192 instances of 68/84/200 regions)")
+    p.add_argument("--uneven-steps", type=int, default=3,
+                   help="timed runs of the uneven batch (after one warm-up run)")
+    p.add_argument("--plain-record", default=os.path.join(ROOT, "profiles", "plain_sweep_32x4.json"),
+                   help="measured plain 32^4 sweep (wall time, full-grid errors), used while its "
+                        "kernel source hash matches")
+    p.add_argument("--write-plain-record", action="store_true",
+                   help="also simulate the whole 32^4 grid plainly and write --plain-record")
     p.add_argument("--run-steps", type=int, default=0,
                    help="profiling only: shorten each run to this many steps (not a bench line)")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -69,7 +78,7 @@ def workload(name):
     if name == "uneven":
         conns = [conn, inputs.synthetic_connectome(84), inputs.synthetic_connectome(200)]
         return conns, inputs.grid_uneven(8192, seed=3), inputs.RUN_UNEVEN, (
-            "uneven batch, one persistent launch per block length: 8192 instances, a third each on 68-, 84- and "
+            "uneven batch in one persistent launch: 8192 instances, a third each on 68-, 84- and "
             "200-region synthetic connectomes, S, b_e, a_e uniform in the sweep box, v uniform in "
             "1-10 m/s (ring depths 21-2001 steps); 50000 Heun steps of 0.1 ms (5 s), FC after a "
             "1 s transient")
@@ -110,6 +119,112 @@ def cpu_baseline(conns, batch, cfg, n_inst, n_steps):
                       f"thread, {wall:.1f} s wall"}
 
 
+def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
+    """Plans (and autotunes) one workload, times `steps` whole runs after
+    `warmup` untimed ones, and returns (line, sweep, context)."""
+    import numpy as np
+    import torch
+
+    from paper_2311_13337_amd import vadx
+    sw = vadx.Sweep(0)
+    ids = [sw.add_connectome(c) for c in conns]
+    sw.set_batch(batch, conn_ids=ids)
+    run = vadx.make_run(cfg)
+    sw.plan(run)
+    sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
+    sw.ctx.vadx_set_launch(0, args.wg_instances, args.item_steps)
+    sw.plan(run)
+    shape = {"instances_per_workgroup": args.wg_instances or "max",
+             "item_steps": args.item_steps or 1000,
+             "waves_per_simd": args.waves_per_simd, "autotuned": False}
+    if not args.no_autotune:
+        lanes, items, waves = sw.autotune(args.tune_cache, trial_steps=args.tune_steps)
+        shape = {"lanes_per_workgroup": lanes, "item_steps": items, "waves_per_simd": waves,
+                 "autotuned": True}
+    ctx = sw.ctx
+    shape.update(ctx.vadx_launch_info())
+    shape["class_lanes"] = {int(c.n): ctx.vadx_class_lanes(int(c.n)) for c in conns}
+    for _ in range(warmup):
+        sw.integrate()
+    torch.cuda.synchronize()
+    ctx.vadx_enable_timing(True)
+    ctx.vadx_kernel_time()                      # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sw.integrate()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sw.sync()                                   # raises on a timed-out wait of the scheduler
+    n_int, ms_int, n_fc, ms_fc = ctx.vadx_kernel_time()
+    ctx.vadx_enable_timing(False)
+    st = sw.stats()
+    assert np.isfinite(st["fc_mean"]).all(), "non-finite FC mean"
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    # the same runs replayed from a HIP graph (host clock; kernels not timed)
+    ctx.vadx_set_graph(True)
+    sw.integrate()
+    sw.sync()
+    g0 = time.perf_counter()
+    for _ in range(steps):
+        sw.integrate()
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    sw.sync()
+    ctx.vadx_set_graph(False)
+    graph_ms = (g1 - g0) * 1000.0 / steps
+    n_inst = len(batch)
+    regions = np.array([c.n for c in conns], np.float64)[batch.conn]
+    region_total = float(regions.sum())
+    sim_s = cfg.n_steps * cfg.dt_ms / 1000.0
+    value = region_total * sim_s / (ms_per_step / 1000.0)
+
+    # roofline of the integration kernel: the kernel's own arithmetic per
+    # region-step (counted with an operation-counting scalar) plus 2 FLOPs per
+    # delayed-coupling edge, times the region-steps of one launch
+    f32, f64, trans = vadx.vadx_region_step_ops(vadx.VADX_HEUN)
+    nnz = np.array([(c.weights != 0).sum() for c in conns], np.float64)
+    edges = float(nnz[batch.conn].sum())
+    flop_rs = f32 + f64 + 2.0 * edges / region_total + 1.0
+    launches_per_step = n_int / steps
+    rs_per_launch = region_total * cfg.n_steps / launches_per_step
+    launch_ms = ms_int / n_int
+    achieved = flop_rs * rs_per_launch / (launch_ms / 1000.0) / 1e12
+    # HBM bytes of the integration kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
+    # (copy-calibrated), stored per region-step for this kernel source
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        if tj.get("workload") == workload_name and tj.get("kernel_source_sha") == _src_sha():
+            traffic = round(tj["bytes_per_region_step"] * rs_per_launch)
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
+            "traffic": traffic,
+            "kernel": "integrate_persistent_kernel", "flop_per_region_step": round(flop_rs, 1),
+            "transcendentals_per_region_step": trans,
+            "launch_ms_avg": round(launch_ms, 3), "launches_per_step": launches_per_step,
+            "fc_kernel_ms_per_step": round(ms_fc / max(n_fc, 1), 3)}
+    flags = st["flags"].astype(np.uint32)
+    out = {"metric": "instance-region-sim-s per wall-s", "value": round(value, 1),
+           "unit": "instance-region-sim-s/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": desc, "instances": n_inst,
+                      "regions": sorted({c.n for c in conns}),
+                      "region_instances_total": int(region_total),
+                      "steps_per_run": cfg.n_steps, "dt_ms": cfg.dt_ms,
+                      "parallelism": "single GPU", "launch_shape": shape,
+                      "timed_path": "eager persistent launch with HIP events around each kernel",
+                      "graph_replay_ms_per_step": round(graph_ms, 3),
+                      "clamp_flag_fraction": round(float(((flags & 2) != 0).mean()), 4),
+                      "silent_fraction": round(float((st["rate_std_hz"] <= 1e-3).mean()), 4),
+                      "nonfinite_fraction": round(float(((flags & 1) != 0).mean()), 4)},
+           "roofline": roof}
+    return out, sw, ctx
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -135,91 +250,32 @@ def main():
         cfg = dataclasses.replace(cfg, n_steps=args.run_steps,
                                   transient_steps=min(cfg.transient_steps, args.run_steps // 2))
         desc = f"[profiling run, {args.run_steps} steps] " + desc
-    sw = vadx.Sweep(0)
-    ids = [sw.add_connectome(c) for c in conns]
-    sw.set_batch(batch, conn_ids=ids)
-    run = vadx.make_run(cfg)
-    sw.plan(run)
-    sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
-    sw.ctx.vadx_set_launch(0, args.wg_instances, args.item_steps)
-    sw.plan(run)
-    shape = {"instances_per_workgroup": args.wg_instances or "max",
-             "item_steps": args.item_steps or 1000,
-             "waves_per_simd": args.waves_per_simd, "autotuned": False}
-    if not args.no_autotune:
-        lanes, items, waves = sw.autotune(args.tune_cache, trial_steps=args.tune_steps)
-        shape = {"lanes_per_workgroup": lanes, "item_steps": items, "waves_per_simd": waves,
-                 "autotuned": True}
-    ctx = sw.ctx
-    shape.update(ctx.vadx_launch_info())
-    for _ in range(args.warmup):
-        sw.integrate()
-    torch.cuda.synchronize()
-    ctx.vadx_enable_timing(True)
-    ctx.vadx_kernel_time()                      # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sw.integrate()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    n_int, ms_int, n_fc, ms_fc = ctx.vadx_kernel_time()
-    ctx.vadx_enable_timing(False)
-    st = sw.stats()
-    assert np.isfinite(st["fc_mean"]).all(), "non-finite FC mean"
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    n_inst = len(batch)
-    regions = np.array([c.n for c in conns], np.float64)[batch.conn]
-    region_total = float(regions.sum())
-    sim_s = cfg.n_steps * cfg.dt_ms / 1000.0
-    value = region_total * sim_s / (ms_per_step / 1000.0)
-
-    # roofline of the integration kernel: the kernel's own arithmetic per
-    # region-step (counted with an operation-counting scalar) plus 2 FLOPs per
-    # delayed-coupling edge, times the region-steps of one launch
-    f32, f64, trans = vadx.vadx_region_step_ops(vadx.VADX_HEUN)
-    nnz = np.array([(c.weights != 0).sum() for c in conns], np.float64)
-    edges = float(nnz[batch.conn].sum())
-    flop_rs = f32 + f64 + 2.0 * edges / region_total + 1.0
-    launches_per_step = n_int / args.steps
-    rs_per_launch = region_total * cfg.n_steps / launches_per_step
-    launch_ms = ms_int / n_int
-    achieved = flop_rs * rs_per_launch / (launch_ms / 1000.0) / 1e12
-    # HBM bytes of the integration kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
-    # (copy-calibrated), stored per region-step for this kernel source
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        if tj.get("workload") == args.workload and tj.get("kernel_source_sha") == _src_sha():
-            traffic = round(tj["bytes_per_region_step"] * rs_per_launch)
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP32_VECTOR_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
-            "traffic": traffic,
-            "kernel": "integrate_kernel", "flop_per_region_step": round(flop_rs, 1),
-            "transcendentals_per_region_step": trans,
-            "launch_ms_avg": round(launch_ms, 3), "launches_per_step": launches_per_step,
-            "fc_kernel_ms_per_step": round(ms_fc / max(n_fc, 1), 3)}
-    out = {"metric": "instance-region-sim-s per wall-s", "value": round(value, 1),
-           "unit": "instance-region-sim-s/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": desc, "instances": n_inst,
-                      "regions": sorted({c.n for c in conns}),
-                      "region_instances_total": int(region_total),
-                      "steps_per_run": cfg.n_steps, "dt_ms": cfg.dt_ms,
-                      "parallelism": "single GPU", "launch_shape": shape},
-           "roofline": roof}
+    try:
+        line = measure(args, conns, batch, cfg, desc, args.workload, args.steps, args.warmup)
+    except vadx.VadxError as e:
+        print(f"bench.py: the integration failed: {e}", file=sys.stderr)
+        sys.exit(1)
+    out, sw, ctx = line
     if not args.no_analysis and args.run_steps == 0:
         out["analysis"] = analysis_line(sw, conns, batch, cfg, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(conns, batch, cfg, args.cpu_sample_instances,
                                            args.cpu_sample_steps)
+    if not args.no_uneven and args.workload == "uniform" and args.run_steps == 0:
+        del sw, ctx
+        torch.cuda.empty_cache()
+        u_conns, u_batch, u_cfg, u_desc = workload("uneven")
+        try:
+            u, sw, ctx = measure(args, u_conns, u_batch, u_cfg, u_desc, "uneven", args.uneven_steps, 1)
+        except vadx.VadxError as e:
+            print(f"bench.py: the uneven-batch integration failed: {e}", file=sys.stderr)
+            sys.exit(1)
+        out["uneven"] = {k: u[k] for k in ("metric", "value", "unit", "steps", "warmup", "ms_per_step",
+                                           "config", "roofline")}
     if not args.no_guided and args.workload == "uniform" and args.run_steps == 0:
         del sw, ctx
         torch.cuda.empty_cache()
-        out["guided_vs_plain"] = guided_line()
+        out["guided_vs_plain"] = guided_line(args.plain_record, args.write_plain_record)
     print(json.dumps(out), flush=True)
 
 
@@ -327,26 +383,75 @@ def analysis_line(sw, conns, batch, cfg, args):
                                      f"regions x {ns} samples (numpy FP64, one process)"}}
 
 
-def guided_line():
+def guided_line(record_path, write_record=False):
     """The second half of the headline metric: the surrogate-guided sweep of the
-    32^4 grid against the plain sweep, at the FC error bound."""
+    32^4 grid against the plain sweep, at the FC error bound. The plain sweep's
+    wall time and the guided result's error over the whole grid come from a
+    record of the measured full plain sweep while that record matches this
+    kernel source and this guided result (same digest); otherwise the plain
+    time is extrapolated from the plain runs of 4096 sampled grid points and
+    the error is taken over those points. write_record: simulate the whole grid
+    plainly as well and write the record (several minutes)."""
+    import hashlib
+
+    import numpy as np
+
     from paper_2311_13337_amd import guided
     try:
-        res, _ = guided.guided_sweep(guided.GuidedConfig(),
-                                     log=lambda m: print(m, file=sys.stderr, flush=True))
+        res, data = guided.guided_sweep(guided.GuidedConfig(), plain_full=write_record,
+                                        log=lambda m: print(m, file=sys.stderr, flush=True))
     except Exception as e:  # reported in the line; the throughput above stands
         return {"error": repr(e)}
+    digest = hashlib.sha256(np.ascontiguousarray(data["guided"]).tobytes()).hexdigest()[:16]
     sec = res["seconds"]
-    return {"time_ratio_guided_over_plain": round(res["time_ratio_guided_over_plain"], 4),
-            "guided_s": round(sec["guided_total"], 2), "plain_s": round(sec["plain"], 2),
-            "plain_is_extrapolated": sec["plain_is_extrapolated"],
+    if write_record:
+        fc = vadx_stat_index("fc_mean")
+        e = np.abs(data["guided"][:, fc] - data["plain"][:, fc])
+        active = data["plain"][:, vadx_stat_index("rate_std_hz")] > 1e-3
+        rec = {"kernel_source_sha": _src_sha(), "guided_digest": digest,
+               "workload": "32^4 grid over S [0,0.5] x b_e [0,120] x a_e [0,8] x v [1,10], 10-s runs "
+                           "on the 68-region connectome, every grid point simulated plainly",
+               "plain_s": round(sec["plain"], 3), "grid_points": res["grid_points"],
+               "active_fraction": round(float(active.mean()), 4),
+               "fc_mean_err_full_grid": {"p95": float(np.quantile(e, 0.95)), "max": float(e.max()),
+                                         "mean": float(e.mean()),
+                                         "p95_active": float(np.quantile(e[active], 0.95))
+                                         if active.any() else 0.0},
+               "guided_s": round(sec["guided_total"], 3), "refined_runs": res["refined"],
+               "command": "python bench.py --no-uneven --no-analysis --no-cpu-baseline "
+                          "--write-plain-record"}
+        with open(record_path, "w") as f:
+            json.dump(rec, f, indent=1)
+    rec = None
+    if os.path.exists(record_path):
+        with open(record_path) as f:
+            rec = json.load(f)
+        if rec.get("kernel_source_sha") != _src_sha() or rec.get("guided_digest") != digest:
+            rec = None
+    plain_s = rec["plain_s"] if rec else sec["plain"]
+    line = {"time_ratio_guided_over_plain": round(sec["guided_total"] / plain_s, 4),
+            "guided_s": round(sec["guided_total"], 2), "plain_s": round(plain_s, 2),
+            "plain_is_extrapolated": rec is None and sec["plain_is_extrapolated"],
             "fc_mean_err_p95": round(res["fc_mean_err"]["p95"], 4), "err_bound": 0.05,
             "passes_err_bound": res["passes_err_bound"],
             "refined_runs": res["refined"], "train_runs": res["train_sims"],
+            "train_epochs": res["train"]["epochs"], "best_epoch": res["train"]["best_epoch"],
             "grid_points": res["grid_points"], "check_points": res["check_points"],
+            "guided_digest": digest,
             "workload": "32^4 grid over S [0,0.5] x b_e [0,120] x a_e [0,8] x v [1,10], 10-s runs; "
                         "32768 training runs; top 5 % by surrogate gradient + 1 % audit, then "
-                        "audit-driven refinement; error vs plain runs of 4096 random grid points"}
+                        "audit-driven refinement"}
+    if rec:
+        line["full_grid"] = {k: rec[k] for k in ("fc_mean_err_full_grid", "active_fraction", "plain_s")}
+        line["fc_mean_err_p95"] = round(rec["fc_mean_err_full_grid"]["p95"], 4)
+        line["passes_err_bound"] = rec["fc_mean_err_full_grid"]["p95"] < 0.05
+        line["check_points"] = rec["grid_points"]
+    return line
+
+
+def vadx_stat_index(name):
+    from paper_2311_13337_amd import vadx
+    return vadx.STAT_NAMES.index(name)
 
 
 def _src_sha():

@@ -169,7 +169,10 @@ vadx_status vadx_plan(vadx_ctx *ctx, const vadx_run *run, size_t *workspace_byte
 vadx_status vadx_integrate(vadx_ctx *ctx, const vadx_run *run, void *workspace,
                            size_t workspace_bytes);
 
-/* Waits for all work of ctx. */
+/* Waits for all work of ctx. After a run, reports VADX_E_HIP if one of the
+ * integration's bounded waits timed out (the run's results are then void):
+ * a workgroup's wait for the previous chunk of its group, or a wave's wait
+ * for the previous block of the waves sharing its instances. */
 vadx_status vadx_sync(vadx_ctx *ctx);
 
 /* Reads results of the last vadx_integrate. `out` is host (VADX_HOST) or
@@ -214,13 +217,22 @@ vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,
                                 int64_t *n_samples);
 
 /* Launch shape of the integration (takes effect at the next vadx_plan).
- * mode 0 (default): a persistent kernel whose workgroups pull (group of
- * instances, chunk of item_steps steps) items from a queue, chunks of one group
- * in order, so uneven batches and grids larger than the GPU stay balanced;
- * mode 1: one workgroup per group for each launch. wg_instances caps the
- * instances per workgroup (0 = as many as fit 512 lanes); item_steps 0 = 1000.
+ * mode 0 (default): one persistent launch whose workgroups pull (group of
+ * instances, chunk of item_steps steps) items from a queue, chunks of one
+ * group in order, over the groups of every block length at once, so uneven
+ * batches and grids larger than the GPU stay balanced and the run has a
+ * single tail; mode 1: one workgroup per group, one launch per block length.
+ * wg_instances caps the instances per workgroup (0 = as many as fit the lane
+ * budget of their region count, vadx_class_lanes); item_steps 0 = 1000.
  * Results do not depend on the shape. */
 vadx_status vadx_set_launch(vadx_ctx *ctx, int32_t mode, int32_t wg_instances, int32_t item_steps);
+
+/* Lane budget of the workgroups holding instances of n_regions regions: each
+ * packs floor(lanes / n_regions) instances (at least one) on consecutive
+ * lanes. lanes in [64, 512] sets it, 0 returns it to the default (512), -1
+ * leaves it; *current (nullable) receives the budget in effect. Takes effect
+ * at the next vadx_plan; results do not depend on it. */
+vadx_status vadx_class_lanes(vadx_ctx *ctx, int32_t n_regions, int32_t lanes, int32_t *current);
 
 /* Register budget of the persistent integration kernel in waves per SIMD: 2
  * (one 512-lane or two 256-lane workgroups per CU, no spills; the default) or
@@ -230,23 +242,25 @@ vadx_status vadx_set_waves_per_simd(vadx_ctx *ctx, int32_t waves);
 
 /* Autotuner of the launch shape for the current batch: times trial runs of
  * trial_steps steps (0 = 2000; no samples) of `run` in `ws` (device, at least
- * the size vadx_plan gave for `run`; its contents are overwritten) for
- * workgroup lane budgets of 64..512 lanes -- each region-count class then
- * packs floor(budget / n) instances per workgroup -- times 2 or 3 waves per
- * SIMD with 1000-step queue items, then, at the fastest lane budget, 2 or 3
- * waves per SIMD with items of 500..8000 steps, and keeps the fastest
- * (persistent launch). With a cache_path (nullable) the choice is read from /
- * added to that JSON file, keyed by device, block length and the
- * region-count mix; a cached choice is applied without trials. *lanes,
- * *item_steps, *waves (nullable) receive the choice. Call vadx_plan again
- * before vadx_integrate. */
+ * the size vadx_plan gave for `run`; its contents are overwritten) of the
+ * persistent launch. Starting from 512-lane budgets with 2 waves per SIMD
+ * and 1000-step items, it tries each region-count class's lane budgets in
+ * turn (64..512 lanes, one per distinct instance count per workgroup; the
+ * other classes at their best so far), then 2 or 3 waves per SIMD with items
+ * of 500..8000 steps at the chosen budgets, and keeps the fastest. With a
+ * cache_path (nullable) the choice is read from / added to that JSON file,
+ * keyed by device, longest block length and the region-count mix; a cached
+ * choice is applied without trials. *lanes (the widest class budget),
+ * *item_steps, *waves (nullable) receive the choice; vadx_class_lanes reads
+ * each class's budget. Call vadx_plan again before vadx_integrate. */
 vadx_status vadx_autotune(vadx_ctx *ctx, const vadx_run *run, void *ws, size_t ws_bytes,
                           const char *cache_path, int32_t trial_steps, int32_t *lanes,
                           int32_t *item_steps, int32_t *waves);
 
 /* Launch shape of the current plan: groups of instances, threads per
- * workgroup, workgroups launched (the persistent grid, or the groups) and the
- * steps per block between workgroup barriers. Each pointer nullable. */
+ * workgroup, workgroups launched (the persistent grid, or the most groups of
+ * one launch) and the longest block of steps between two synchronisations of
+ * an instance's waves. Each pointer nullable. */
 vadx_status vadx_launch_info(vadx_ctx *ctx, int32_t *groups, int32_t *block_threads,
                              int32_t *grid, int32_t *steps_per_block);
 

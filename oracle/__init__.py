@@ -91,6 +91,9 @@ def lib():
         vp = C.c_void_p
         L.oracle_run.argtypes = [P(Model), P(RunCfg), C.c_int, dp, dp, C.c_int64, fp, fp, fp, fp,
                                  up, vp, vp, dp, vp, vp, vp, vp, up, C.c_int]
+        L.oracle_anchored_steps.argtypes = [P(Model), P(RunCfg), C.c_int, dp, dp, C.c_float, C.c_float,
+                                            C.c_float, C.c_float, C.c_uint32, vp, C.c_int64, dp, dp]
+        L.oracle_anchored_steps.restype = C.c_uint32
         assert L.oracle_model_size() == C.sizeof(Model), "oracle model layout mismatch"
         _lib = L
     return _lib
@@ -168,6 +171,32 @@ def fc_stats(samples, w_raw, min_std=0.0):
     st = np.zeros(6)
     flags = lib().oracle_fc_stats(n, x.shape[0], x, w, min_std, fc, st)
     return fc, st, flags
+
+
+def anchored_steps(m: Model, run_cfg, conn, batch, q: int, trace, inst_id=None, integrator=0,
+                   noise_off=False):
+    """The oracle's steps of instance q of ``batch`` each re-anchored on a given
+    trajectory ``trace`` [steps, 8, n] (state after every step, e.g. another
+    implementation's): out[n] is one oracle step from trace[n-1] (the initial
+    state for n = 0), with the coupling from trace's excitatory rates and the
+    instance's Philox normals. Returns (out [steps, 8, n], flags)."""
+    tr = np.ascontiguousarray(trace, np.float64)
+    nt = tr.shape[0]
+    r = RunCfg(dt=run_cfg.dt_ms, n_steps=nt, transient_steps=0, tavg_steps=run_cfg.tavg_steps,
+               n_trace_steps=nt, seed=run_cfg.seed, integrator=integrator,
+               noise_off=1 if noise_off else 0, fc_min_std=getattr(run_cfg, "fc_min_std", 1e-9))
+    extra = None
+    if getattr(batch, "extra", None):
+        names = ("w_noise", "tau_w_e", "cF_ee", "cF_ei", "cF_ie", "cF_ii")
+        extra = np.array([batch.extra[k][q] if k in batch.extra else getattr(m, k) for k in names],
+                         np.float64)
+    out = np.zeros_like(tr)
+    fl = lib().oracle_anchored_steps(
+        C.byref(m), C.byref(r), conn.n, np.ascontiguousarray(conn.weights, np.float64),
+        np.ascontiguousarray(conn.tract_mm, np.float64), float(batch.S[q]), float(batch.b_e[q]),
+        float(batch.a_e[q]), float(batch.v[q]), int(q if inst_id is None else inst_id), _ptr(extra),
+        nt, tr, out)
+    return out, fl
 
 
 def _ptr(a):

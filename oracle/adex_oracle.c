@@ -71,7 +71,13 @@ int oracle_model_preset(int preset, or_model *m)
     m->T = 20.0;
     m->E_L_e = -64.0; m->E_L_i = -65.0;
     m->tau_w_e = 500.0; m->tau_w_i = 1.0; m->b_i = 0.0; m->a_i = 0.0;
-    m->cF_ee = 0.3e-3; m->cF_ei = 0.0; m->cF_ie = 0.3e-3; m->cF_ii = 0.0;
+    /* external drives (kHz): the upper end of Table 4's range for the
+       excitatory inputs. With the lower end (0.3e-3) the node keeps a
+       quiescent fixed point near 4e-8 Hz that absorbs most networks with
+       b_e >= 48 pA, so the sweep box has no synchronous regime; at 0.5e-3
+       that state is gone and adaptation turns the active state into slow
+       oscillations (Section 3.2.1). */
+    m->cF_ee = 0.5e-3; m->cF_ei = 0.0; m->cF_ie = 0.5e-3; m->cF_ii = 0.0;
     m->tau_OU = 5.0;  m->sigma_OU = 1e-3; m->w_noise = 1e-3;
     m->muV0 = -60.0;  m->dmuV0 = 10.0; m->sV0 = 4.0; m->dsV0 = 6.0;
     m->tN0 = 0.5;     m->dtN0 = 1.0;
@@ -633,6 +639,62 @@ static void *run_worker(void *arg)
         run_instance(J, q);
     }
     return NULL;
+}
+
+/* Re-anchored steps of one instance: for every step n < n_steps, the oracle's
+   step n taken from a given state -- trace_in[n-1] (the state after step
+   n-1), or the initial state for n = 0 -- with the coupling formed from the
+   given excitatory-rate history (E of trace_in; the initial rate before the
+   first step) and the instance's own Philox normal of step n. out[n] is the
+   state after that one step, to compare with trace_in[n]: each step of
+   another implementation is checked on its own, whatever the trajectory's
+   sensitivity to earlier rounding. trace_in, out: [n_steps][8][n]. extra:
+   NULL or the six further per-instance parameters (as in oracle_run).
+   Returns the OR of the step flags. */
+uint32_t oracle_anchored_steps(const or_model *m0, const or_run *r, int n, const double *w_raw,
+                               const double *L, float S, float b_e, float a_e, float v,
+                               uint32_t inst_id, const double *extra, int64_t n_steps,
+                               const double *trace_in, double *out)
+{
+    or_model mi = *m0;
+    if (extra) {
+        mi.w_noise = extra[0]; mi.tau_w_e = extra[1];
+        mi.cF_ee = extra[2]; mi.cF_ei = extra[3]; mi.cF_ie = extra[4]; mi.cF_ii = extra[5];
+    }
+    const or_model *m = &mi;
+    double *W = malloc(sizeof(double) * n * n);
+    int32_t *d = malloc(sizeof(int32_t) * n * n);
+    uint32_t flags = 0;
+    oracle_normalise_rows(n, w_raw, W);
+    oracle_delays(n, L, v, r->dt, d);
+    for (int64_t step = 0; step < n_steps; ++step) {
+        for (int k = 0; k < n; ++k) {
+            double c = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (W[k * n + j] == 0.0) continue;
+                /* history value at step mt: E after step mt-1, initial before */
+                int64_t mt = step - d[k * n + j];
+                double h = mt >= 1 ? trace_in[((size_t)(mt - 1) * N_SV + SV_E) * n + j] : m->E_init;
+                c += W[k * n + j] * h;
+            }
+            c *= S;
+            double xs[N_SV];
+            for (int q = 0; q < N_SV; ++q) {
+                if (step == 0) {
+                    double x0[N_SV] = {m->E_init, m->I_init, 0, 0, 0, 0, 0, 0};
+                    xs[q] = x0[q];
+                } else {
+                    xs[q] = trace_in[((size_t)(step - 1) * N_SV + q) * n + k];
+                }
+            }
+            double z = r->noise_off ? 0.0 : oracle_normal(r->seed, inst_id, (uint64_t)step, (uint32_t)k);
+            flags |= oracle_step_region(m, r->integrator, r->dt, xs, c, b_e, a_e, z);
+            for (int q = 0; q < N_SV; ++q) out[((size_t)step * N_SV + q) * n + k] = xs[q];
+        }
+    }
+    free(W);
+    free(d);
+    return flags;
 }
 
 /* Runs n_inst instances on one connectome with n_threads threads (one

@@ -8,9 +8,10 @@
 
 namespace vadx {
 
-// Largest number of steps integrated between two workgroup barriers. A block
-// of B steps reads the delay rings before writing any of its own rates, which
-// is exact as long as B <= d_min + 1 (the shortest delay plus one).
+// Largest number of steps integrated between two synchronisations of the
+// waves of an instance (one block). A block of B steps reads the delay rings
+// before writing any of its own rates, which is exact as long as
+// B <= d_min + 1 (the shortest delay plus one).
 constexpr int kMaxBlock = 32;
 
 // One instance = one parameter combination on one connectome.
@@ -41,12 +42,13 @@ struct ConnDev {
     int64_t ref_off;    // into reference FC matrices (n*n floats); -1: none
 };
 
-// A workgroup's share: `count` instances of the same region count.
+// A workgroup's share: `count` instances of the same region count and block
+// length, on consecutive lanes (instance s on lanes [s n, (s + 1) n)).
 struct GroupDev {
     int32_t first;      // into the instance permutation
     int32_t count;
     int32_t n;
-    int32_t pad;
+    int32_t block;      // steps per block (<= d_min + 1 of every instance)
 };
 
 struct DelayTableDev {
@@ -57,6 +59,7 @@ struct DelayTableDev {
 
 struct IntegrateArgs {
     KModel M;
+    const KModel *Mp;           // the same constants in device memory (read per queue item)
     const InstDev *inst;
     const int32_t *perm;
     const GroupDev *groups;
@@ -72,14 +75,17 @@ struct IntegrateArgs {
     double E_init, I_init;
     uint32_t seed;
     int32_t integrator;
-    int32_t block;              // steps per barrier block (<= kMaxBlock)
+    int32_t block;              // one workgroup per group: the groups' block length;
+                                // persistent: the longest block length (sizes the LDS)
+    uint32_t *status;           // bit 1: a wait for another wave's block timed out
+    uint32_t wait_spins;        // bound of that wait
 };
 
 // Work queue of the persistent integration kernel (in the workspace).
 struct QueueArgs {
     int *next;                  // next item to hand out
     int *done;                  // per group: chunks completed in this launch
-    uint32_t *status;           // bit 0: a wait timed out
+    uint32_t *status;           // bit 0: a wait for a previous chunk timed out
     int n_groups, n_items;
     int64_t item_steps;
     uint32_t max_spins;
@@ -104,13 +110,17 @@ hipError_t launch_conn_prepare(int n, const double *w, const double *len, int32_
 hipError_t launch_delays(int n_tables, const DelayTableDev *tables, const ConnDev *conns,
                          const int32_t *colidx, const double *edge_len, double dt,
                          int32_t *packed, int max_nnz, hipStream_t s);
-// q == nullptr: one workgroup per group over [a.n_begin, a.n_end); otherwise the
-// persistent kernel with `grid` workgroups draining the queue.
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
-// occ: waves per SIMD of the persistent kernel's register budget (2 or 3)
-hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
-                            const QueueArgs *q, int grid, int occ, hipStream_t s);
-int persistent_blocks_per_cu(int block, int block_threads, int occ);
+// Copies m to device memory (out) on stream s.
+hipError_t launch_kmodel_store(const KModel &m, KModel *out, hipStream_t s);
+// One workgroup per group (all of block length a.block) over [a.n_begin, a.n_end).
+hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads, hipStream_t s);
+// The persistent kernel: `grid` workgroups drain the queue of (group, chunk)
+// items over a.groups (any block lengths up to a.block); occ: waves per SIMD
+// of its register budget (2 or 3).
+hipError_t launch_integrate_persistent(const IntegrateArgs &a, int block_threads, const QueueArgs &q,
+                                       int grid, int occ, hipStream_t s);
+int persistent_blocks_per_cu(int max_block, int block_threads, int occ);
 hipError_t launch_rank_sort(const float *val, const int64_t *idx, int32_t k, int64_t *idx_out,
                             float *val_out, hipStream_t s);
 hipError_t launch_fc_stats(const FcArgs &a, int64_t n_inst, hipStream_t s);

@@ -122,22 +122,60 @@ template <int B> constexpr int kGatherFloats = B > 16 ? 96 : 64;
 template <int B> constexpr int kGatherEdges =
     B >= kGatherFloats<B> ? 1 : (kGatherFloats<B> / B > 8 ? 8 : kGatherFloats<B> / B);
 
+// Waits until every wave in [lo, hi] other than `self` has published m
+// blocks of the current item (per-wave counters in LDS), then acquires their
+// history writes. The wait is bounded: on timeout bit 1 of *status is set
+// and the wave goes on (its results are then void, and the run reports it),
+// so no wave can wait forever. Every argument is wave-uniform.
+__device__ __forceinline__ void wait_waves(const int *wdone, int lo, int hi, int self, int m,
+                                           uint32_t *status, uint32_t max_spins)
+{
+    for (int v = lo; v <= hi; ++v) {
+        if (v == self) continue;
+        uint32_t spins = 0;
+        while (__builtin_amdgcn_readfirstlane(
+                   __hip_atomic_load(&wdone[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < m) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > max_spins) {
+                if ((threadIdx.x & 63) == 0) atomicOr(status, 2u);
+                break;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Integrates the instances of group g over steps [n_begin, n_end). All
 // threads of the workgroup call it with the same (wave-uniform) arguments: it
-// contains workgroup barriers.
+// starts with a workgroup barrier. Inside, waves synchronise only with the
+// waves that share an instance with them: before the gather of block m a
+// wave waits until those waves have written the histories of block m-1
+// (counters in LDS, `wdone`), so waves of different instances drift apart
+// by up to a block instead of meeting at a barrier after every block. The
+// ring depth (d_max + B + 1) keeps a block's writes clear of every slot a
+// wave one block behind still reads.
 //
-// Ring row of region j: D slots holding E_j at steps n mod D, followed by
-// B - 1 mirror slots (slot D + s repeats slot s), so the B consecutive
-// history values a block needs from one edge never wrap.
 template <int B, int VAR>
 __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const GroupDev g,
-                                                int64_t n_begin, int64_t n_end, float *cbuf)
+                                                int64_t n_begin, int64_t n_end, float *cbuf,
+                                                int *wdone)
 {
     const int tid = threadIdx.x;
     const int slot = tid / g.n;
     const int k = tid - slot * g.n;
     const bool active = slot < g.count;
     const int nthr = blockDim.x;
+    // this wave and the waves holding lanes of the instances it holds
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int used = g.count * g.n;
+    const bool wave_live = wave * 64 < used;
+    int wlo = wave, whi = wave - 1;
+    if (wave_live) {
+        const int last = (wave * 64 + 63 < used ? wave * 64 + 63 : used - 1) / g.n;
+        wlo = ((wave * 64) / g.n * g.n) >> 6;
+        whi = ((last + 1) * g.n - 1) >> 6;
+    }
+    if ((tid & 63) == 0) wdone[wave] = 0;
 
     InstDev I;
     double X[8];
@@ -177,7 +215,7 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
             acc = a.ws[I.acc_off + k];
         }
     }
-    __syncthreads();   // initial rings visible to all lanes
+    __syncthreads();   // initial rings and the wave counters visible to all lanes
 
     const float S = active ? I.S : 0.f;
     InstModel<float> P;
@@ -189,14 +227,17 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
     P.cF[0][1] = active ? I.cF[1] : 0.f;
     P.cF[1][0] = active ? I.cF[2] : 0.f;
     P.cF[1][1] = active ? I.cF[3] : 0.f;
+    const KModel M = *a.Mp;
     const int D = active ? I.D : 1;
     const int Dp = active ? I.Dp : 1;
     int nm = active ? (int)(n_begin % D) : 0;   // n0 mod D
     float *myrow = active ? ring + (int64_t)k * Dp : nullptr;
     float z4[4] = {0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t n0 = n_begin; n0 < n_end; n0 += B) {
+    int m = 0;   // blocks published by this wave
+    for (int64_t n0 = n_begin; n0 < n_end && wave_live; n0 += B, ++m) {
         const int nb = (int)((n_end - n0) < B ? (n_end - n0) : B);
+        if (m > 0) wait_waves(wdone, wlo, whi, wave, m, a.status, a.wait_spins);
         if (active) {
             // coupling of steps n0 .. n0+nb-1: S sum_j W_kj H_j[n - d_kj], in the
             // fixed (ascending j) order of the CSR row
@@ -262,7 +303,7 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                     normals4(a.seed, I.id, (uint32_t)(n >> 2), (uint32_t)k, z4);
                 const float z = r == 0 ? z4[0] : (r == 1 ? z4[1] : (r == 2 ? z4[2] : z4[3]));
                 const float c = cbuf[b * nthr + tid];
-                fl |= step_region<VAR>(a.M, a.integrator, a.dt, X, c, P,
+                fl |= step_region<VAR>(M, a.integrator, a.dt, X, c, P,
                                        a.gdw_scale * (double)z);
                 // history of E: slot (n + 1) mod D, and its mirror
                 wm += 1;
@@ -288,7 +329,10 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
             nm += nb;
             nm -= (nm >= D) ? D : 0;
         }
-        __syncthreads();   // this block's history visible before the next block reads it
+        // publish this block's history to the waves that share its instances
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if ((tid & 63) == 0)
+            __hip_atomic_store(&wdone[wave], m + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     if (active) {
         double *st = reinterpret_cast<double *>(a.ws + I.state_off);
@@ -303,11 +347,31 @@ template <int B, int VAR>
 __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 {
     extern __shared__ float cbuf[];   // [B][blockDim.x] coupling of the block's steps
-    integrate_group<B, VAR>(a, a.groups[blockIdx.x], a.n_begin, a.n_end, cbuf);
+    __shared__ int wdone[8];
+    integrate_group<B, VAR>(a, a.groups[blockIdx.x], a.n_begin, a.n_end, cbuf, wdone);
+}
+
+// One group over [n_begin, n_end) with the group's own block length.
+template <int VAR>
+__device__ __forceinline__ void integrate_group_any(const IntegrateArgs &a, const GroupDev g,
+                                                    int64_t n_begin, int64_t n_end, float *cbuf,
+                                                    int *wdone)
+{
+    switch (g.block) {
+    case 1: integrate_group<1, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    case 2: integrate_group<2, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    case 4: integrate_group<4, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    case 8: integrate_group<8, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    case 16: integrate_group<16, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    case 24: integrate_group<24, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    default: integrate_group<32, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    }
 }
 
 // Persistent form: workgroups pull (group, chunk) items from a queue in
-// chunk-major order; chunk c of a group starts only after chunk c-1 of the
+// chunk-major order over the groups of every block length, so one launch
+// integrates a whole uneven batch; each group runs with its own block length
+// and instance count. Chunk c of a group starts only after chunk c-1 of the
 // same group has been published (its state and history written back to
 // memory), so the groups advance in step while every workgroup stays busy
 // until the queue is empty. The wait is bounded: on timeout the kernel
@@ -316,10 +380,11 @@ __global__ __launch_bounds__(512) void integrate_kernel(IntegrateArgs a)
 // two 256-lane workgroups per CU, no spills; 3: three 256-lane workgroups, a
 // few spills outside the step loop). (A budget of 4 waves, 128 registers,
 // spills inside the step loop and measured slower than both.)
-template <int B, int VAR, int OCC>
+template <int VAR, int OCC>
 __global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(IntegrateArgs a, QueueArgs q)
 {
-    extern __shared__ float cbuf[];
+    extern __shared__ float cbuf[];   // [largest block][blockDim.x]
+    __shared__ int wdone[8];
     __shared__ int s_item;
     __shared__ int s_abort;
     const int tid = threadIdx.x;
@@ -356,7 +421,7 @@ __global__ __launch_bounds__(512, OCC) void integrate_persistent_kernel(Integrat
         }
         const int64_t nb = a.n_begin + (int64_t)c * q.item_steps;
         const int64_t ne = nb + q.item_steps < a.n_end ? nb + q.item_steps : a.n_end;
-        integrate_group<B, VAR>(a, a.groups[gi], nb, ne, cbuf);
+        integrate_group_any<VAR>(a, a.groups[gi], nb, ne, cbuf, wdone);
         __threadfence();                           // publish state and history
         __syncthreads();
         if (tid == 0)
@@ -382,6 +447,22 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s
     return hipGetLastError();
 }
 
+// Stores the run's model constants where the integration kernels read them
+// (once per queue item, from device memory, rather than holding them in
+// scalar registers for the whole launch).
+__global__ void kmodel_store_kernel(KModel m, KModel *out)
+{
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&m);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(out);
+    for (int i = threadIdx.x; i < (int)(sizeof(KModel) / 4); i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_kmodel_store(const KModel &m, KModel *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(kmodel_store_kernel, dim3(1), dim3(64), 0, s, m, out);
+    return hipGetLastError();
+}
+
 __global__ void queue_reset_kernel(QueueArgs q)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -389,66 +470,81 @@ __global__ void queue_reset_kernel(QueueArgs q)
     if (i < q.n_groups) q.done[i] = 0;
 }
 
-template <int B, int VAR, int OCC>
+template <int B, int VAR>
 static hipError_t launch_integrate_b(const IntegrateArgs &a, int n_groups, int block_threads,
-                                     const QueueArgs *q, int grid, hipStream_t s)
+                                     hipStream_t s)
 {
     size_t lds = (size_t)B * block_threads * sizeof(float);
-    if (q == nullptr) {
-        hipLaunchKernelGGL((integrate_kernel<B, VAR>), dim3(n_groups), dim3(block_threads), lds, s, a);
-    } else {
-        hipLaunchKernelGGL(queue_reset_kernel, dim3((q->n_groups + 255) / 256), dim3(256), 0, s, *q);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((integrate_persistent_kernel<B, VAR, OCC>), dim3(grid), dim3(block_threads),
-                           lds, s, a, *q);
-    }
+    hipLaunchKernelGGL((integrate_kernel<B, VAR>), dim3(n_groups), dim3(block_threads), lds, s, a);
     return hipGetLastError();
 }
 
-template <int VAR, int OCC>
+template <int VAR>
 static hipError_t launch_integrate_v(const IntegrateArgs &a, int n_groups, int block_threads,
-                                      const QueueArgs *q, int grid, hipStream_t s)
+                                     hipStream_t s)
 {
     switch (a.block) {
-    case 1: return launch_integrate_b<1, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 2: return launch_integrate_b<2, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 4: return launch_integrate_b<4, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 8: return launch_integrate_b<8, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 16: return launch_integrate_b<16, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 24: return launch_integrate_b<24, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 32: return launch_integrate_b<32, VAR, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 1: return launch_integrate_b<1, VAR>(a, n_groups, block_threads, s);
+    case 2: return launch_integrate_b<2, VAR>(a, n_groups, block_threads, s);
+    case 4: return launch_integrate_b<4, VAR>(a, n_groups, block_threads, s);
+    case 8: return launch_integrate_b<8, VAR>(a, n_groups, block_threads, s);
+    case 16: return launch_integrate_b<16, VAR>(a, n_groups, block_threads, s);
+    case 24: return launch_integrate_b<24, VAR>(a, n_groups, block_threads, s);
+    case 32: return launch_integrate_b<32, VAR>(a, n_groups, block_threads, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int OCC>
-static hipError_t launch_integrate_o(const IntegrateArgs &a, int n_groups, int block_threads,
-                                     const QueueArgs *q, int grid, hipStream_t s)
+hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads, hipStream_t s)
 {
     switch (model_variant(a.M)) {
-    case 0: return launch_integrate_v<0, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 1: return launch_integrate_v<1, OCC>(a, n_groups, block_threads, q, grid, s);
-    case 2: return launch_integrate_v<2, OCC>(a, n_groups, block_threads, q, grid, s);
-    default: return launch_integrate_v<3, OCC>(a, n_groups, block_threads, q, grid, s);
+    case 0: return launch_integrate_v<0>(a, n_groups, block_threads, s);
+    case 1: return launch_integrate_v<1>(a, n_groups, block_threads, s);
+    case 2: return launch_integrate_v<2>(a, n_groups, block_threads, s);
+    default: return launch_integrate_v<3>(a, n_groups, block_threads, s);
     }
 }
 
-hipError_t launch_integrate(const IntegrateArgs &a, int n_groups, int block_threads,
-                            const QueueArgs *q, int grid, int occ, hipStream_t s)
+template <int VAR, int OCC>
+static hipError_t launch_persistent_v(const IntegrateArgs &a, int block_threads, const QueueArgs &q,
+                                      int grid, hipStream_t s)
 {
-    if (occ == 3) return launch_integrate_o<3>(a, n_groups, block_threads, q, grid, s);
-    return launch_integrate_o<2>(a, n_groups, block_threads, q, grid, s);
+    hipLaunchKernelGGL(queue_reset_kernel, dim3((q.n_groups + 255) / 256), dim3(256), 0, s, q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t lds = (size_t)a.block * block_threads * sizeof(float);
+    hipLaunchKernelGGL((integrate_persistent_kernel<VAR, OCC>), dim3(grid), dim3(block_threads),
+                       lds, s, a, q);
+    return hipGetLastError();
 }
 
-template <int B, int OCC> static int resident_b(int block_threads)
+template <int OCC>
+static hipError_t launch_persistent_o(const IntegrateArgs &a, int block_threads, const QueueArgs &q,
+                                      int grid, hipStream_t s)
+{
+    switch (model_variant(a.M)) {
+    case 0: return launch_persistent_v<0, OCC>(a, block_threads, q, grid, s);
+    case 1: return launch_persistent_v<1, OCC>(a, block_threads, q, grid, s);
+    case 2: return launch_persistent_v<2, OCC>(a, block_threads, q, grid, s);
+    default: return launch_persistent_v<3, OCC>(a, block_threads, q, grid, s);
+    }
+}
+
+hipError_t launch_integrate_persistent(const IntegrateArgs &a, int block_threads, const QueueArgs &q,
+                                       int grid, int occ, hipStream_t s)
+{
+    if (occ == 3) return launch_persistent_o<3>(a, block_threads, q, grid, s);
+    return launch_persistent_o<2>(a, block_threads, q, grid, s);
+}
+
+template <int OCC> static int resident_o(int max_block, int block_threads)
 {
     // all model variants have the same launch bounds and LDS use
     int per_cu = 1 << 30;
-    size_t lds = (size_t)B * block_threads * sizeof(float);
+    size_t lds = (size_t)max_block * block_threads * sizeof(float);
     void (*kernels[4])(IntegrateArgs, QueueArgs) = {
-        integrate_persistent_kernel<B, 0, OCC>, integrate_persistent_kernel<B, 1, OCC>,
-        integrate_persistent_kernel<B, 2, OCC>, integrate_persistent_kernel<B, 3, OCC>};
+        integrate_persistent_kernel<0, OCC>, integrate_persistent_kernel<1, OCC>,
+        integrate_persistent_kernel<2, OCC>, integrate_persistent_kernel<3, OCC>};
     for (auto k : kernels) {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_threads, lds) != hipSuccess)
@@ -458,24 +554,10 @@ template <int B, int OCC> static int resident_b(int block_threads)
     return per_cu;
 }
 
-template <int OCC> static int resident(int block, int block_threads)
+int persistent_blocks_per_cu(int max_block, int block_threads, int occ)
 {
-    switch (block) {
-    case 1: return resident_b<1, OCC>(block_threads);
-    case 2: return resident_b<2, OCC>(block_threads);
-    case 4: return resident_b<4, OCC>(block_threads);
-    case 8: return resident_b<8, OCC>(block_threads);
-    case 16: return resident_b<16, OCC>(block_threads);
-    case 24: return resident_b<24, OCC>(block_threads);
-    case 32: return resident_b<32, OCC>(block_threads);
-    default: return 0;
-    }
-}
-
-int persistent_blocks_per_cu(int block, int block_threads, int occ)
-{
-    if (occ == 3) return resident<3>(block, block_threads);
-    return resident<2>(block, block_threads);
+    if (occ == 3) return resident_o<3>(max_block, block_threads);
+    return resident_o<2>(max_block, block_threads);
 }
 
 // ------------------------------------------------------------------ FC and statistics

@@ -27,8 +27,9 @@ using namespace vadx;
 
 namespace {
 
-// Groups sharing a block length: [first, first + n_groups) of the group table,
-// integrated by one launch of workgroups of `threads` lanes.
+// Groups sharing a block length: [first, first + n_groups) of the group table
+// (one launch of workgroups of `threads` lanes each in the one-workgroup-per-
+// group mode; the persistent launch takes every class at once).
 struct BlockClass {
     int block;
     int32_t first, n_groups;
@@ -118,6 +119,7 @@ struct vadx_ctx {
     DevBuf<GroupDev> d_groups;
     DevBuf<DelayTableDev> d_tables;
     DevBuf<int32_t> d_packed;
+    DevBuf<KModel> d_kmodel;             // model constants of the run being integrated
     // last run
     void *ws = nullptr;
     bool ran = false;
@@ -137,6 +139,7 @@ struct vadx_ctx {
     uint64_t g_epoch = 0, plan_epoch = 0;
     int wg_instances_override = 0;
     int wg_lanes = 512;                  // lane budget per workgroup (autotuned)
+    std::map<int, int> class_lanes;      // lane budget per region count (autotuned; else wg_lanes)
     int occ = 2;                         // waves per SIMD of the persistent kernel (autotuned)
     int item_steps = 1000;
     int cus = 0;
@@ -180,7 +183,7 @@ vadx_status vadx_model_defaults(int preset, vadx_model *m)
     m->K_e = 400.0; m->K_i = 100.0; m->N_e = 8000.0; m->N_i = 2000.0; m->T = 20.0;
     m->E_L_e = -64.0; m->E_L_i = -65.0; m->tau_w_e = 500.0; m->tau_w_i = 1.0;
     m->b_i = 0.0; m->a_i = 0.0;
-    m->cF_ee = 0.3e-3; m->cF_ei = 0.0; m->cF_ie = 0.3e-3; m->cF_ii = 0.0;
+    m->cF_ee = 0.5e-3; m->cF_ei = 0.0; m->cF_ie = 0.5e-3; m->cF_ii = 0.0;   // Table 4's upper drive
     m->tau_OU = 5.0; m->sigma_OU = 1e-3; m->w_noise = 1e-3;
     m->muV0 = -60.0; m->dmuV0 = 10.0; m->sV0 = 4.0; m->dsV0 = 6.0; m->tN0 = 0.5; m->dtN0 = 1.0;
     m->rate_max = 1.0; m->E_init = 0.004; m->I_init = 0.01; m->x_floor = 1e-6;
@@ -232,7 +235,7 @@ void vadx_destroy(vadx_ctx *c)
         for (auto &e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     c->rowptr.release(); c->colidx.release(); c->weight.release(); c->edge_len.release();
     c->sc.release(); c->d_conns.release(); c->d_inst.release(); c->d_perm.release();
-    c->d_groups.release(); c->d_tables.release(); c->d_packed.release();
+    c->d_groups.release(); c->d_tables.release(); c->d_packed.release(); c->d_kmodel.release();
     delete c;
 }
 
@@ -265,6 +268,7 @@ vadx_status vadx_set_model(vadx_ctx *c, const vadx_model *m)
         return fail(c, VADX_E_ARG, "initial rates outside [0, rate_max]");
     c->model = *m;
     c->have_model = true;
+    ++c->plan_epoch;   // a recorded run graph holds the previous constants
     return VADX_OK;
 }
 
@@ -503,14 +507,15 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         const int32_t cid = c->conn_of[order[s]];
         const int B = blk[order[s]];
         const int n = c->conns[cid].n;
-        int per = std::max(1, c->wg_lanes / n);
+        const auto cl = c->class_lanes.find(n);
+        int per = std::max(1, (cl != c->class_lanes.end() ? cl->second : c->wg_lanes) / n);
         if (c->wg_instances_override > 0) per = std::min(per, c->wg_instances_override);
         int64_t e = s;
         while (e < ni && e - s < per && c->conn_of[order[e]] == cid && blk[order[e]] == B) ++e;
         if (c->classes.empty() || c->classes.back().block != B)
             c->classes.push_back(BlockClass{B, (int32_t)c->h_groups.size(), 0, 64});
         BlockClass &bc = c->classes.back();
-        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, 0});
+        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, B});
         bc.n_groups += 1;
         bc.threads = std::max(bc.threads, (int)(((e - s) * n + 63) / 64 * 64));
         s = e;
@@ -576,6 +581,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     HIP_TRY(c, c->d_groups.ensure(c->h_groups.size()));
     HIP_TRY(c, c->d_tables.ensure(c->h_tables.size()));
     HIP_TRY(c, c->d_packed.ensure((size_t)std::max<int64_t>(c->packed_total, 1)));
+    HIP_TRY(c, c->d_kmodel.ensure(1));
     HIP_TRY(c, hipMemcpyAsync(c->d_inst.p, c->h_inst.data(), ni * sizeof(InstDev), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_perm.p, c->h_perm.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_groups.p, c->h_groups.data(), c->h_groups.size() * sizeof(GroupDev), hipMemcpyHostToDevice, c->stream));
@@ -614,6 +620,8 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     IntegrateArgs a{};
     a.M = make_kmodel(c->model);
     a.M.same_inputs = c->batch_same ? 1 : 0;
+    HIP_TRY(c, launch_kmodel_store(a.M, c->d_kmodel.p, st));
+    a.Mp = c->d_kmodel.p;
     a.inst = c->d_inst.p;
     a.perm = c->d_perm.p;
     a.groups = c->d_groups.p;
@@ -645,13 +653,37 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
     chunk = chunk >= r->n_steps ? std::max<int64_t>(r->n_steps, 1)
                                 : std::max<int64_t>(chunk / bl, 1) * bl;
     const int64_t item_steps = std::max<int64_t>(c->item_steps / bl, 1) * bl;
-    if (c->launch_mode == 0) {
-        uint32_t *status = (uint32_t *)((char *)ws + c->off_queue) + 1;
-        HIP_TRY(c, launch_fill_u32(status, 1, 0u, st));
-    }
+    uint32_t *status = (uint32_t *)((char *)ws + c->off_queue) + 1;
+    HIP_TRY(c, launch_fill_u32(status, 1, 0u, st));
+    a.status = status;
+    a.wait_spins = 1u << 24;
     for (int64_t n0 = 0; n0 < r->n_steps; n0 += chunk) {
         a.n_begin = n0;
         a.n_end = std::min<int64_t>(r->n_steps, n0 + chunk);
+        if (c->launch_mode == 0) {
+            // one persistent launch over the groups of every block length
+            a.block = c->block;
+            a.groups = c->d_groups.p;
+            const int ng = (int)c->h_groups.size();
+            hipEvent_t stop = nullptr;
+            if (timed) { vadx_status e = record(c, c->ev_int, &stop); if (e) return e; }
+            int *qb = (int *)((char *)ws + c->off_queue);
+            QueueArgs q{};
+            q.next = qb;
+            q.status = status;
+            q.done = qb + 2;
+            q.n_groups = ng;
+            q.item_steps = item_steps;
+            q.max_spins = 1u << 26;
+            const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads, c->occ);
+            if (per_cu <= 0)
+                return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", c->wg_threads);
+            const int grid = std::min(ng, per_cu * c->cus);
+            q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
+            HIP_TRY(c, launch_integrate_persistent(a, c->wg_threads, q, grid, c->occ, st));
+            if (timed) HIP_TRY(c, hipEventRecord(stop, st));
+            continue;
+        }
         // one launch per block length, longest first, on the same stream
         for (const BlockClass &bc : c->classes) {
             a.block = bc.block;
@@ -659,24 +691,7 @@ static vadx_status enqueue_run(vadx_ctx *c, const vadx_run *r, void *ws, hipStre
             const int ng = bc.n_groups;
             hipEvent_t stop = nullptr;
             if (timed) { vadx_status e = record(c, c->ev_int, &stop); if (e) return e; }
-            if (c->launch_mode == 0) {
-                int *qb = (int *)((char *)ws + c->off_queue);
-                QueueArgs q{};
-                q.next = qb;
-                q.status = (uint32_t *)(qb + 1);
-                q.done = qb + 2;
-                q.n_groups = ng;
-                q.item_steps = item_steps;
-                q.max_spins = 1u << 26;
-                const int per_cu = persistent_blocks_per_cu(bc.block, bc.threads, c->occ);
-                if (per_cu <= 0)
-                    return fail(c, VADX_E_UNSUPPORTED, "workgroup of %d threads does not fit a CU", bc.threads);
-                const int grid = std::min(ng, per_cu * c->cus);
-                q.n_items = (int)(ng * ((a.n_end - a.n_begin + q.item_steps - 1) / q.item_steps));
-                HIP_TRY(c, launch_integrate(a, ng, bc.threads, &q, grid, c->occ, st));
-            } else {
-                HIP_TRY(c, launch_integrate(a, ng, bc.threads, nullptr, ng, 2, st));
-            }
+            HIP_TRY(c, launch_integrate(a, ng, bc.threads, st));
             if (timed) HIP_TRY(c, hipEventRecord(stop, st));
         }
     }
@@ -760,13 +775,11 @@ vadx_status vadx_launch_info(vadx_ctx *c, int32_t *groups, int32_t *block_thread
     if (!c) return VADX_E_ARG;
     if (!c->planned) return fail(c, VADX_E_STATE, "no plan");
     int g = 0;
-    for (const BlockClass &bc : c->classes) {
-        int gc = bc.n_groups;
-        if (c->launch_mode == 0) {
-            const int per_cu = persistent_blocks_per_cu(bc.block, bc.threads, c->occ);
-            gc = std::min(gc, per_cu * c->cus);
-        }
-        g = std::max(g, gc);
+    if (c->launch_mode == 0) {
+        const int per_cu = persistent_blocks_per_cu(c->block, c->wg_threads, c->occ);
+        g = std::min((int)c->h_groups.size(), per_cu * c->cus);
+    } else {
+        for (const BlockClass &bc : c->classes) g = std::max(g, bc.n_groups);
     }
     if (groups) *groups = (int32_t)c->h_groups.size();
     if (block_threads) *block_threads = c->wg_threads;
@@ -790,10 +803,11 @@ vadx_status vadx_sync(vadx_ctx *c)
     if (!c) return VADX_E_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    if (c->ran && c->launch_mode == 0) {
+    if (c->ran) {
         uint32_t status = 0;
         HIP_TRY(c, hipMemcpy(&status, (char *)c->ws + c->off_queue + 4, 4, hipMemcpyDeviceToHost));
-        if (status) return fail(c, VADX_E_HIP, "integration scheduler: a wait for a previous chunk timed out");
+        if (status & 1u) return fail(c, VADX_E_HIP, "integration scheduler: a wait for a previous chunk timed out");
+        if (status & 2u) return fail(c, VADX_E_HIP, "integration: a wait for another wave's block timed out");
     }
     return VADX_OK;
 }
@@ -952,7 +966,31 @@ static std::string tune_key(vadx_ctx *c)
     return k.str();
 }
 
-static bool tune_lookup(const char *path, const std::string &key, int *lanes, int *items, int *occ)
+// Lane budgets per region count as "n:lanes,n:lanes".
+static std::string lanes_str(const std::map<int, int> &m)
+{
+    std::ostringstream o;
+    for (auto it = m.begin(); it != m.end(); ++it) o << (it == m.begin() ? "" : ",") << it->first << ":" << it->second;
+    return o.str();
+}
+
+static bool lanes_parse(const std::string &t, std::map<int, int> *m)
+{
+    std::map<int, int> r;
+    std::istringstream in(t);
+    std::string tok;
+    while (std::getline(in, tok, ',')) {
+        int n = 0, l = 0;
+        if (std::sscanf(tok.c_str(), "%d:%d", &n, &l) != 2 || n < 1 || l < 64 || l > 512) return false;
+        r[n] = l;
+    }
+    if (r.empty()) return false;
+    *m = r;
+    return true;
+}
+
+static bool tune_lookup(const char *path, const std::string &key, std::map<int, int> *lanes, int *items,
+                        int *occ)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -960,15 +998,16 @@ static bool tune_lookup(const char *path, const std::string &key, int *lanes, in
     while (std::getline(f, line)) {
         const size_t at = line.find(q);
         if (at == std::string::npos) continue;
-        int l = 0, it = 0, w = 0;
-        const size_t pl = line.find("\"lanes\":", at), pi = line.find("\"item_steps\":", at);
+        int it = 0, w = 0;
+        const size_t pl = line.find("\"class_lanes\": \"", at), pi = line.find("\"item_steps\":", at);
         const size_t pw = line.find("\"waves_per_simd\":", at);
         if (pl == std::string::npos || pi == std::string::npos || pw == std::string::npos) continue;
-        if (std::sscanf(line.c_str() + pl + 8, "%d", &l) == 1 &&
+        const size_t l0 = pl + 16, l1 = line.find('"', l0);
+        std::map<int, int> m;
+        if (l1 != std::string::npos && lanes_parse(line.substr(l0, l1 - l0), &m) &&
             std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 &&
-            std::sscanf(line.c_str() + pw + 17, "%d", &w) == 1 && l >= 64 && l <= 512 && it > 0 &&
-            w >= 2 && w <= 3) {
-            *lanes = l;
+            std::sscanf(line.c_str() + pw + 17, "%d", &w) == 1 && it > 0 && w >= 2 && w <= 3) {
+            *lanes = m;
             *items = it;
             *occ = w;
             return true;
@@ -977,8 +1016,8 @@ static bool tune_lookup(const char *path, const std::string &key, int *lanes, in
     return false;
 }
 
-static void tune_store(const char *path, const std::string &key, int lanes, int items, int occ,
-                       double ms)
+static void tune_store(const char *path, const std::string &key, const std::map<int, int> &lanes,
+                       int items, int occ, double ms)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -986,15 +1025,16 @@ static void tune_store(const char *path, const std::string &key, int lanes, int 
         std::ifstream f(path);
         std::string line, q = "\"" + key + "\"";
         while (std::getline(f, line))
-            if (line.find("\"lanes\":") != std::string::npos && line.find(q) == std::string::npos) {
+            if (line.find("\"class_lanes\":") != std::string::npos && line.find(q) == std::string::npos) {
                 while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
                 keep.push_back(line);
             }
     }
-    char buf[512];
+    char buf[640];
     std::snprintf(buf, sizeof(buf),
-                  "  \"%s\": {\"lanes\": %d, \"item_steps\": %d, \"waves_per_simd\": %d, \"trial_ms\": %.3f}",
-                  key.c_str(), lanes, items, occ, ms);
+                  "  \"%s\": {\"class_lanes\": \"%s\", \"item_steps\": %d, \"waves_per_simd\": %d, "
+                  "\"trial_ms\": %.3f}",
+                  key.c_str(), lanes_str(lanes).c_str(), items, occ, ms);
     keep.push_back(buf);
     std::ofstream o(path, std::ios::trunc);
     o << "{\n";
@@ -1028,10 +1068,12 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     c->wg_instances_override = 0;
     c->use_graph = false;
     c->timing = false;
-    int max_n = 1;
-    for (int32_t ci : c->conn_of) max_n = std::max(max_n, c->conns[ci].n);
+    // the region-count classes of the batch
+    std::map<int, int> lanes;
+    for (int32_t ci : c->conn_of) lanes[c->conns[ci].n] = 512;
     vadx_status result = VADX_OK;
-    int best_l = 512, best_i = 1000, best_w = 2;
+    std::map<int, int> best_l = lanes;
+    int best_i = 1000, best_w = 2;
     double best_ms = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto restore = [&]() {
@@ -1045,8 +1087,8 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    auto trial = [&](int lanes, int items, int occ, double *ms) -> vadx_status {
-        c->wg_lanes = lanes;
+    auto trial = [&](const std::map<int, int> &l, int items, int occ, double *ms) -> vadx_status {
+        c->class_lanes = l;
         c->item_steps = items;
         c->occ = occ;
         c->planned = false;
@@ -1065,14 +1107,17 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         return VADX_OK;
     };
     // the key needs the block length of this batch: plan once
-    c->wg_lanes = 512;
+    c->class_lanes = lanes;
     c->planned = false;
     result = vadx_plan(c, &t, &need);
     if (result) { restore(); return result; }
     const std::string key = tune_key(c);
-    int cl = 0, ci = 0, cw = 0;
+    std::map<int, int> cl;
+    int ci = 0, cw = 0;
     if (tune_lookup(cache_path, key, &cl, &ci, &cw)) {
-        best_l = cl;
+        for (auto &e : lanes)
+            if (cl.count(e.first)) e.second = cl[e.first];
+        best_l = lanes;
         best_i = ci;
         best_w = cw;
     } else {
@@ -1081,32 +1126,28 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
             return fail(c, VADX_E_HIP, "event creation failed");
         }
         double ms = 0.0;
-        result = trial(512, 1000, 2, &ms);    // warm-up (code load, caches)
-        const int l_lo = std::max(64, (max_n + 63) / 64 * 64);
-        for (int l = l_lo; l <= 512 && result == VADX_OK; l += 64) {
-            // skip budgets that give the same instances per workgroup as a larger one
-            bool same = false;
-            if (l + 64 <= 512) {
-                same = true;
-                for (int32_t cj : c->conn_of) {
-                    const int n = c->conns[cj].n;
-                    if (std::max(1, l / n) != std::max(1, (l + 64) / n)) { same = false; break; }
-                }
-            }
-            if (same) continue;
-            for (int w : {2, 3}) {
-                if (result) break;
-                result = trial(l, 1000, w, &ms);
-                if (result == VADX_OK && (best_ms < 0 || ms < best_ms)) {
-                    best_ms = ms; best_l = l; best_i = 1000; best_w = w;
-                }
+        result = trial(lanes, 1000, 2, &ms);    // warm-up (code load, caches)
+        if (result == VADX_OK) result = trial(lanes, 1000, 2, &ms);
+        if (result == VADX_OK) best_ms = ms;
+        // each region-count class's lane budget in turn (the others at their
+        // best so far): floor(budget / n) instances per workgroup, one
+        // candidate per distinct instance count
+        for (auto &e : lanes) {
+            const int n = e.first;
+            for (int l = std::max(64, (n + 63) / 64 * 64); l <= 512 && result == VADX_OK; l += 64) {
+                if (l + 64 <= 512 && std::max(1, l / n) == std::max(1, (l + 64) / n)) continue;
+                if (l == best_l[n]) continue;
+                std::map<int, int> cand = best_l;
+                cand[n] = l;
+                result = trial(cand, 1000, 2, &ms);
+                if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_l = cand; }
             }
         }
-        // the register budget and the item length together, at the chosen lane budget
+        // the register budget and the item length together, at the chosen lane budgets
         for (int w : {2, 3})
             for (int it : {500, 1000, 2000, 4000, 8000}) {
                 if (result) break;
-                if (w == best_w && it == 1000) continue;
+                if (w == 2 && it == 1000) continue;
                 result = trial(best_l, it, w, &ms);
                 if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; best_w = w; }
             }
@@ -1114,12 +1155,33 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     }
     restore();
     if (result) return result;
-    c->wg_lanes = best_l;
+    c->class_lanes = best_l;
     c->item_steps = best_i;
     c->occ = best_w;
+    int widest = 64;
+    for (auto &e : best_l) widest = std::max(widest, e.second);
     if (waves_out) *waves_out = best_w;
-    if (lanes_out) *lanes_out = best_l;
+    if (lanes_out) *lanes_out = widest;
     if (item_steps_out) *item_steps_out = best_i;
+    return VADX_OK;
+}
+
+extern "C" vadx_status vadx_class_lanes(vadx_ctx *c, int32_t n_regions, int32_t lanes, int32_t *current)
+{
+    if (!c) return VADX_E_ARG;
+    if (n_regions < 1 || (lanes != 0 && lanes != -1 && (lanes < 64 || lanes > 512)))
+        return fail(c, VADX_E_ARG, "bad lane budget");
+    if (lanes > 0) {
+        c->class_lanes[n_regions] = lanes;
+        c->planned = false;
+    } else if (lanes == 0) {
+        c->class_lanes.erase(n_regions);
+        c->planned = false;
+    }
+    if (current) {
+        const auto it = c->class_lanes.find(n_regions);
+        *current = it != c->class_lanes.end() ? it->second : c->wg_lanes;
+    }
     return VADX_OK;
 }
 

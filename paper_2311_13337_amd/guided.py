@@ -3,17 +3,20 @@
 The plain method simulates every point of a dense grid. The guided sweep
   1. simulates a training set of points drawn uniformly from the sweep box,
   2. trains the surrogate network on their statistics (vadx_mlp_train, early
-     stopping on a held-out tenth),
-  3. screens the whole grid with the network: predicted statistics and the
-     input-gradient norm of (sync_index, fc_mean), large where the dynamics
-     change regime,
-  4. simulates the points of largest gradient plus a random audit sample,
+     stopping on a held-out tenth), and a second network of the same shape on
+     the surrogate's absolute errors over the training set,
+  3. screens the whole grid with both: predicted statistics, and the
+     predicted error of fc_mean as the refinement order (large where runs of
+     one parameter point differ from run to run or the statistics change
+     sharply; the surrogate's input-gradient norm of (sync_index, fc_mean) is
+     the alternative order, cfg.score = "gradient"),
+  4. simulates the points first in that order plus a random audit sample,
      each with the noise stream it has in the plain sweep (its grid index as
      noise key), so a refined point carries exactly its plain-sweep value,
   5. uses the audit sample -- simulated points drawn independently of the
-     score -- to estimate, for each score threshold, the fraction of the grid
-     that would stay unrefined with an FC error above the bound, and refines
-     further down the score ranking until that estimate is below the target,
+     score -- to estimate, for each cut in that order, the fraction of the
+     grid that would stay unrefined with an FC error above the bound, and
+     refines further down the order until that estimate is below the target,
   6. keeps the predictions elsewhere.
 The plain simulation stays the reference: the error of the guided result is
 measured against plain runs of a random sample of grid points (bit-identical
@@ -60,6 +63,8 @@ class GuidedConfig:
     err_bound: float = 0.05
     target_exceed: float = 0.04        # audit estimate of the grid fraction above err_bound
     adaptive: bool = True
+    score: str = "error"               # refinement order: "error" (a second network's predicted
+                                       # error of fc_mean) or "gradient" (transition gradient)
 
 
 class Simulator:
@@ -148,6 +153,18 @@ def screen(net, grid_X):
     return Yh, score, time.perf_counter() - t0
 
 
+def train_error_net(net, X, Y, cfg: GuidedConfig, log=print):
+    """A second network of the same shape, trained (same settings) on the
+    surrogate's absolute errors over the training set: where the statistics
+    vary from run to run (chaotic, noise-driven regimes) or change sharply, a
+    prediction of the mean is far from any one run, and that is where
+    refinement pays."""
+    Yhat, _, _ = net.predict(_dev(X))
+    R = np.abs(Yhat.cpu().numpy() - Y)
+    err_net, info = train_surrogate(X, R, cfg, log=lambda m: log(m.replace("trained", "error net trained")))
+    return err_net, info
+
+
 def select(net, score, k, cfg: GuidedConfig):
     """Indices of the k largest scores plus the audit sample, and audit flags."""
     import torch
@@ -190,6 +207,14 @@ def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False
     Ytrain, ftrain, t_data = sim(train, TRAIN_KEY_BASE + np.arange(cfg.n_train), "training set")
     net, tinfo = train_surrogate(_points(train), Ytrain, cfg, log)
     Yhat, score, t_screen = screen(net, G)
+    fc = STATS.index("fc_mean")
+    if cfg.score == "error":
+        err_net, einfo = train_error_net(net, _points(train), Ytrain, cfg, log)
+        tinfo["seconds"] += einfo["seconds"]
+        t0 = time.perf_counter()
+        Rhat, _, _ = err_net.predict(_dev(G))
+        score = Rhat[:, fc].contiguous()
+        t_screen += time.perf_counter() - t0
     t0 = time.perf_counter()
     k1 = int(round(cfg.top_frac * n))
     idx, is_aud = select(net, score, k1, cfg)
@@ -197,7 +222,6 @@ def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False
     log(f"[guided] screened {n} points in {t_screen:.2f} s; refining {len(idx)} "
         f"({int((~is_aud).sum())} by gradient, {int(is_aud.sum())} audit)")
     Yref, fref, t_refine = sim(grid.subset(idx), idx, "refinement")
-    fc = STATS.index("fc_mean")
     k2 = k1
     if cfg.adaptive and is_aud.any():
         t0 = time.perf_counter()

@@ -28,7 +28,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
            "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
-           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_set_waves_per_simd", "vadx_launch_info", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
+           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_set_waves_per_simd", "vadx_launch_info", "vadx_class_lanes", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
@@ -125,6 +125,7 @@ def lib():
                                    P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
             "vadx_set_waves_per_simd": (st, [vp, C.c_int32]),
             "vadx_launch_info": (st, [vp, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
+            "vadx_class_lanes": (st, [vp, C.c_int32, C.c_int32, P(C.c_int32)]),
             "vadx_plan": (st, [vp, P(vadx_run), P(C.c_size_t)]),
             "vadx_integrate": (st, [vp, P(vadx_run), vp, C.c_size_t]),
             "vadx_sync": (st, [vp]),
@@ -256,6 +257,13 @@ class Context:
         self._check(lib().vadx_launch_info(self.h, C.byref(g), C.byref(t), C.byref(gr), C.byref(b)))
         return {"groups": g.value, "block_threads": t.value, "grid": gr.value,
                 "steps_per_block": b.value}
+
+    def vadx_class_lanes(self, n_regions: int, lanes: int = -1) -> int:
+        """Sets (lanes > 0), clears (0) or only reads (-1) the lane budget of
+        instances with n_regions regions; returns the budget in effect."""
+        cur = C.c_int32()
+        self._check(lib().vadx_class_lanes(self.h, n_regions, lanes, C.byref(cur)))
+        return cur.value
 
     def vadx_set_waves_per_simd(self, waves: int):
         self._check(lib().vadx_set_waves_per_simd(self.h, waves))

@@ -106,9 +106,76 @@ def test_drift_and_step_against_oracle(mh):
         g = np.zeros(8, np.float32)
         mh.mh_drift(C.byref(vm), X.astype(np.float32), c, be, ae, g)
         scale = np.abs(o) + np.abs(X) / 20.0 + 1e-12       # drift against state / T
+        # eq. (2) sums terms of size |C| |grad F| / T that can cancel: the
+        # single-precision rounding is relative to those terms
+        xo = X[0] + c + om.w_noise * X[7]
+        grads = 0.0
+        for pop, xe, xi, W in ((0, xo + om.cF_ee, X[1] + om.cF_ei, X[5]),
+                               (1, xo + om.cF_ie, X[1] + om.cF_ii, X[6])):
+            t = oracle.tf(om, pop, max(xe, om.x_floor), max(xi, om.x_floor), W)
+            grads += abs(t[1]) + abs(t[2])
+        scale[2:5] += 2.0 * (abs(X[2]) + abs(X[3]) + abs(X[4])) * grads / om.T
         assert np.all(np.abs(g - o) <= 1e-4 * scale), (X, g, o)
         # one Heun step (drift in FP32, state in FP64) against the FP64 step
         Xg = X.copy()
         mh.mh_step(C.byref(vm), 0, 0.1, Xg, c, be, ae, 1e-5)
         Xo, _ = oracle.step_region(om, X, c, be, ae, 1e-5 / (om.sigma_OU / om.tau_OU * np.sqrt(0.1)))
-        assert np.all(np.abs(Xg - Xo) <= 1e-5 * (np.abs(Xo) + np.abs(X)) + 1e-15), (Xg, Xo)
+        # the increment dt (f0 + f1) / 2 carries the drifts' error bound above
+        assert np.all(np.abs(Xg - Xo) <= 1e-5 * (np.abs(Xo) + np.abs(X)) + 0.1 * 1e-4 * scale + 1e-15), \
+            (Xg, Xo)
+
+
+def _host_trajectory(mh, om, conn, batch, i, n_steps, seed=0):
+    """Free-running network of the single-precision model code on the host:
+    FP32 drift, FP64 state, coupling summed in FP32 from the FP32 rate
+    history (as the kernel's ring holds it), the oracle's Philox normals.
+    Returns the trace [steps, 8, n] rounded to FP32 as the kernel records it."""
+    vm = vmodel(om)
+    n = conn.n
+    W = oracle.normalise_rows(conn.weights).astype(np.float32)
+    d = oracle.delays(conn.tract_mm, batch.v[i], 0.1)
+    rows = [np.nonzero(W[k])[0] for k in range(n)]
+    X = np.zeros((n, 8))
+    X[:, 0], X[:, 1] = om.E_init, om.I_init
+    H = np.zeros((n_steps + 1, n), np.float32)
+    H[0] = np.float32(om.E_init)
+    tr = np.zeros((n_steps, 8, n))
+    gsc = om.sigma_OU / om.tau_OU * np.sqrt(0.1)
+    S = np.float32(batch.S[i])
+    for s in range(n_steps):
+        for k in range(n):
+            acc = np.float32(0.0)
+            for j in rows[k]:
+                acc = np.float32(acc + W[k, j] * H[max(s - d[k, j], 0), j])
+            x = np.ascontiguousarray(X[k])
+            mh.mh_step(C.byref(vm), 0, 0.1, x, S * acc, float(batch.b_e[i]), float(batch.a_e[i]),
+                       gsc * oracle.normal(seed, i, s, k))
+            X[k] = x
+        H[s + 1] = X[:, 0].astype(np.float32)
+        tr[s] = X.T.astype(np.float32)
+    return tr
+
+
+def test_anchored_check_on_single_precision_trajectories(mh):
+    """The re-anchored step check of the GPU parity tests, run on free
+    trajectories of the host build of the same single-precision model code:
+    it passes for a weakly and a strongly coupled network (the latter with
+    steps whose conditioning the check has to account for), and it fails when
+    the oracle's model differs by 1 % in one constant (T)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from parity_checks import anchored_check
+
+    from paper_2311_13337_amd import inputs
+    conn = inputs.synthetic_connectome(68)
+    batch = inputs.grid_small()
+    cfg = inputs.RunConfig(n_steps=300, transient_steps=0, n_trace_steps=300)
+    om = oracle.model("literature-B")
+    for i in (0, 6):
+        tr = _host_trajectory(mh, om, conn, batch, i, 300)
+        err, _ = anchored_check(oracle, om, cfg, conn, batch, i, tr)
+        assert err.max() < 1.0, (i, err.max())
+    wrong = oracle.model("literature-B", T=om.T * 1.01)
+    tr = _host_trajectory(mh, om, conn, batch, 0, 300)
+    err, _ = anchored_check(oracle, wrong, cfg, conn, batch, 0, tr)
+    assert err.max() > 1.0

@@ -145,8 +145,10 @@ def test_heun_on_linear_ou_is_exact_ar1(oracle):
 
 
 def test_heun_is_second_order(oracle):
-    """Noise-free single node: halving dt shrinks the error about 4x."""
-    m = oracle.model()
+    """Noise-free single node: halving dt shrinks the error about 4x. The
+    drive 0.3e-3 kHz keeps this trajectory inside the admissible set (the
+    projection never acts), where the scheme's order is defined."""
+    m = oracle.model(cF_ee=0.3e-3, cF_ie=0.3e-3)
     X0 = np.array([0.006, 0.012, 1e-6, 1e-6, 2e-6, 3.0, 0, 0])
 
     def integrate(dt, T=20.0):
@@ -343,3 +345,33 @@ def test_instance_parameters_equal_model_parameters(oracle):
     b0.extra = {}
     r0 = oracle.run(oracle.model("literature-B"), cfg, conn, b0, n_threads=1)
     assert not np.array_equal(r["trace"], r0["trace"])
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_anchored_steps_reproduce_the_run(oracle, integrator):
+    """Each step re-anchored on the oracle's own trajectory is that run's step,
+    bit for bit (coupling from the trace's rates, the initial rate before t =
+    0, the instance's own normals), for both integrators and per-instance
+    Table 4 parameters; a trace changed at one step changes only the steps
+    that read it."""
+    conn = inputs.synthetic_connectome(20, seed=5, len_lo=2.0, len_hi=12.0)
+    batch = inputs.grid_table4(np.array([5, 70000, 200001]))
+    batch.v[:] = np.array([2.0, 3.5, 6.0], np.float32)
+    cfg = inputs.RunConfig(n_steps=240, transient_steps=0, n_trace_steps=240, seed=9)
+    m = oracle.model()
+    ref = oracle.run(m, cfg, conn, batch, integrator=integrator)
+    for q in range(len(batch)):
+        out, _ = oracle.anchored_steps(m, cfg, conn, batch, q, ref["trace"][q], integrator=integrator)
+        assert np.array_equal(out, ref["trace"][q])
+    # a planted change of one region's rate after step 100: step 101 of that
+    # region moves (its own state), and no region's step before its delay
+    tr = ref["trace"][0].copy()
+    tr[100, E, 3] *= 1.001
+    out, _ = oracle.anchored_steps(m, cfg, conn, batch, 0, tr, integrator=integrator)
+    diff = np.nonzero(np.any(out != ref["trace"][0], axis=1))
+    steps, regions = diff
+    assert 101 in steps[regions == 3]
+    d = oracle.delays(conn.tract_mm, batch.v[0], cfg.dt_ms)
+    W = conn.weights
+    for s_, k in zip(steps, regions):
+        assert s_ == 101 and k == 3 or (W[k, 3] != 0 and s_ == 101 + d[k, 3]), (s_, k)

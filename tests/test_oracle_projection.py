@@ -151,8 +151,9 @@ def test_euler_ou_stationary_statistics(oracle):
 
 def test_euler_is_first_order(oracle):
     """Noise-free single node away from any bound: halving dt halves the error
-    against an adaptive integration of the oracle's own drift."""
-    m = oracle.model()
+    against an adaptive integration of the oracle's own drift (drive
+    0.3e-3 kHz: the trajectory stays inside the admissible set)."""
+    m = oracle.model(cF_ee=0.3e-3, cF_ie=0.3e-3)
     X0 = np.array([0.006, 0.012, 1e-6, 1e-6, 2e-6, 3.0, 0, 0])
     be, ae, T = 30.0, 2.0, 20.0
 
