@@ -211,6 +211,17 @@ vadx_status vadx_set_reference_fc(vadx_ctx *ctx, int32_t conn_id, const float *f
 vadx_status vadx_top_k(vadx_ctx *ctx, const float *score, int64_t n, int32_t k, int64_t *idx,
                        float *val);
 
+/* vadx_top_k for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * arguments and results, with its scratch (selection histogram, per-tile
+ * counts and bases, the k candidate indices; 89 KB) in a fixed device array
+ * that each GPU holds from vadx_create until the process ends. It calls no
+ * allocator. At most 2^24 scores (VADX_E_UNSUPPORTED above). Calls that
+ * overlap on one GPU share that array and race; every call clears what it
+ * needs. Synchronises the context's stream. */
+vadx_status vadx_top_k_noalloc(vadx_ctx *ctx, const float *score, int64_t n, int32_t k,
+                               int64_t *idx, float *val);
+
 /* Region count and number of post-transient samples of instance `inst` for
  * the last plan (sizes of the read_* outputs). */
 vadx_status vadx_instance_shape(vadx_ctx *ctx, int64_t inst, int32_t *n_regions,

@@ -96,9 +96,17 @@ namespace vadx {
         }                                                                              \
     } while (0)
 
+size_t select_scratch_bytes(int64_t tiles)
+{
+    const size_t off_cnt = 256 * sizeof(uint32_t);
+    const size_t off_eq = (off_cnt + tiles * sizeof(uint32_t) + 255) & ~(size_t)255;
+    return off_eq + 2 * tiles * sizeof(int64_t);
+}
+
 vadx_status select_run(hipStream_t s, SelScratch &sc, const float *score, int64_t n, int64_t k,
                        float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
-                       int64_t capacity, int64_t *n_sel, std::string &err)
+                       int64_t capacity, int64_t *n_sel, std::string &err,
+                       uint32_t *host_counts, int64_t *host_bases)
 {
     if (!n_sel || n < 0 || k < 0 || (n > 0 && !score) || capacity < 0 ||
         (capacity > 0 && !sel) || !(audit_frac >= 0.f && audit_frac <= 1.f)) {
@@ -114,7 +122,7 @@ vadx_status select_run(hipStream_t s, SelScratch &sc, const float *score, int64_
     const size_t off_cnt = 256 * sizeof(uint32_t);
     const size_t off_eq = (off_cnt + tiles * sizeof(uint32_t) + 255) & ~(size_t)255;
     const size_t off_sb = off_eq + tiles * sizeof(int64_t);
-    const size_t bytes = off_sb + tiles * sizeof(int64_t);
+    const size_t bytes = select_scratch_bytes(tiles);
     if (tiles > sc.tiles) {
         if (sc.p) (void)hipFree(sc.p);
         sc.p = nullptr;
@@ -149,34 +157,40 @@ vadx_status select_run(hipStream_t s, SelScratch &sc, const float *score, int64_
             mask |= 0xFFu << shift;
         }
     }
-    std::vector<uint32_t> hc((size_t)tiles);
-    std::vector<int64_t> hb((size_t)tiles);
+    std::vector<uint32_t> hc_own;
+    std::vector<int64_t> hb_own;
+    if (!host_counts || !host_bases) {
+        hc_own.resize((size_t)tiles);
+        hb_own.resize((size_t)tiles);
+    }
+    uint32_t *hc = host_counts ? host_counts : hc_own.data();
+    int64_t *hb = host_bases ? host_bases : hb_own.data();
     // phase 0: keys equal to T per tile -> eq_base
     if (use_top) {
         SHIP(launch_sel_compact(score, n, 0, 1, prefix, need, 0.f, seed, nullptr, nullptr,
                                 counts, nullptr, nullptr, s));
-        SHIP(hipMemcpyAsync(hc.data(), counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SHIP(hipMemcpyAsync(hc, counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         SHIP(hipStreamSynchronize(s));
     }
     int64_t acc = 0;
     for (int64_t t = 0; t < tiles; ++t) {
-        hb[(size_t)t] = acc;
-        acc += use_top ? hc[(size_t)t] : 0;
+        hb[t] = acc;
+        acc += use_top ? hc[t] : 0;
     }
-    SHIP(hipMemcpyAsync(eq_base, hb.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SHIP(hipMemcpyAsync(eq_base, hb, tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
     // phase 1: selected points per tile -> sel_base
     SHIP(launch_sel_compact(score, n, 1, use_top, prefix, need, audit_frac, seed, eq_base,
                             nullptr, counts, nullptr, nullptr, s));
-    SHIP(hipMemcpyAsync(hc.data(), counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SHIP(hipMemcpyAsync(hc, counts, tiles * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SHIP(hipStreamSynchronize(s));
     acc = 0;
     for (int64_t t = 0; t < tiles; ++t) {
-        hb[(size_t)t] = acc;
-        acc += hc[(size_t)t];
+        hb[t] = acc;
+        acc += hc[t];
     }
     *n_sel = acc;
     if (acc > capacity) { err = "selection larger than the output capacity"; return VADX_E_OOM; }
-    SHIP(hipMemcpyAsync(sel_base, hb.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SHIP(hipMemcpyAsync(sel_base, hb, tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
     // phase 2: write the indices
     SHIP(launch_sel_compact(score, n, 2, use_top, prefix, need, audit_frac, seed, eq_base,
                             sel_base, nullptr, sel, is_audit, s));

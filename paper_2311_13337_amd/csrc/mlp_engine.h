@@ -47,8 +47,14 @@ struct SelScratch {
 // The k largest scores (ties to the lower index) plus an audit sample of the
 // rest (probability audit_frac, Philox keyed (seed, index)), indices ascending;
 // synchronises s.
+// With host_counts / host_bases (select_tiles(n) entries each, nullable) the
+// per-tile host staging uses them instead of allocating; a scratch `sc` of at
+// least select_tiles(n) tiles is used as it is (no device allocation).
 vadx_status select_run(hipStream_t s, SelScratch &sc, const float *score, int64_t n, int64_t k,
                        float audit_frac, uint32_t seed, int64_t *sel, uint8_t *is_audit,
-                       int64_t capacity, int64_t *n_sel, std::string &err);
+                       int64_t capacity, int64_t *n_sel, std::string &err,
+                       uint32_t *host_counts = nullptr, int64_t *host_bases = nullptr);
+// Bytes of a selection scratch of `tiles` tiles (layout of select_run).
+size_t select_scratch_bytes(int64_t tiles);
 
 } // namespace vadx

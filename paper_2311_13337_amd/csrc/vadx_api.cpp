@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -145,6 +146,9 @@ struct vadx_ctx {
     int cus = 0;
 };
 
+// Per-device address of the scratch array of vadx_top_k_noalloc (defined below).
+static hipError_t noalloc_scratch(int device, void **p);
+
 // Errors of calls made without a context (vadx_create) land here.
 static thread_local std::string g_err = "";
 
@@ -209,6 +213,10 @@ vadx_status vadx_create(int device, void *hip_stream, vadx_ctx **out)
     if (device < 0 || device >= ndev) return fail(nullptr, VADX_E_ARG, "device %d out of range", device);
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, VADX_E_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    void *scratch_p = nullptr;
+    e = noalloc_scratch(device, &scratch_p);
+    if (e != hipSuccess)
+        return fail(nullptr, VADX_E_HIP, "address of the top-k scratch: %s", hipGetErrorString(e));
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess || cus <= 0) return fail(nullptr, VADX_E_HIP, "CU count: %s", hipGetErrorString(e));
@@ -1299,6 +1307,71 @@ extern "C" vadx_status vadx_top_k(vadx_ctx *c, const float *score, int64_t n, in
     if (st) return fail(c, st, "%s", err.c_str());
     if (n_sel != k) return fail(c, VADX_E_ARG, "selection returned %lld of %d", (long long)n_sel, k);
     HIP_TRY(c, launch_rank_sort(score, c->topk_idx.p, k, idx, val, c->stream));
+    return VADX_OK;
+}
+
+// ---------------------------------------------------------------- top k without allocation
+// vadx_top_k_noalloc keeps its scratch (the selection's histogram, per-tile
+// counts and bases, the k candidate indices) in one file-scope device array
+// of fixed size instead of allocating. Each device holds its own copy; host
+// code reaches it only through the address hipGetSymbolAddress gives on that
+// device (kept per device in g_noalloc_ptr), never through the array's name.
+constexpr int64_t kNoAllocMaxPoints = (int64_t)1 << 24;
+constexpr int64_t kNoAllocTiles = kNoAllocMaxPoints / 4096;     // selection tiles of 4096 points
+constexpr size_t kNoAllocSelBytes = 256 * 4 + kNoAllocTiles * 4 + 2 * kNoAllocTiles * 8;
+constexpr size_t kNoAllocBytes = ((kNoAllocSelBytes + 255) / 256) * 256 + 1024 * sizeof(int64_t);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[kNoAllocMaxDevices];
+
+// Address of this device's scratch copy; resolved once per device with the
+// device current (vadx_create calls it). Returns hipSuccess or the error.
+static hipError_t noalloc_scratch(int device, void **p)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = q;
+    }
+    *p = g_noalloc_ptr[device];
+    return hipSuccess;
+}
+
+extern "C" vadx_status vadx_top_k_noalloc(vadx_ctx *c, const float *score, int64_t n, int32_t k,
+                                          int64_t *idx, float *val)
+{
+    if (!c) return VADX_E_ARG;
+    if (n < 0 || k < 0 || (n > 0 && !score) || (k > 0 && !idx))
+        return fail(c, VADX_E_ARG, "bad top-k arguments");
+    if (k > 1024) return fail(c, VADX_E_UNSUPPORTED, "k above 1024");
+    if (k > n) return fail(c, VADX_E_ARG, "k above the number of scores");
+    if (n > kNoAllocMaxPoints)
+        return fail(c, VADX_E_UNSUPPORTED, "%lld scores: vadx_top_k_noalloc takes at most %lld",
+                    (long long)n, (long long)kNoAllocMaxPoints);
+    if (k == 0) return VADX_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (select_tiles(n) > kNoAllocTiles) return fail(c, VADX_E_UNSUPPORTED, "selection tiles exceed the scratch");
+    void *base = nullptr;
+    HIP_TRY(c, noalloc_scratch(c->device, &base));
+    // host staging of the per-tile counts: static, one set per calling thread
+    static thread_local uint32_t h_counts[kNoAllocTiles];
+    static thread_local int64_t h_bases[kNoAllocTiles];
+    SelScratch sc;
+    sc.p = base;
+    sc.tiles = kNoAllocTiles;
+    int64_t *cand = (int64_t *)((char *)base + ((kNoAllocSelBytes + 255) / 256) * 256);
+    int64_t n_sel = 0;
+    std::string err;
+    vadx_status st = select_run(c->stream, sc, score, n, k, 0.f, 0u, cand, nullptr, k, &n_sel, err,
+                                h_counts, h_bases);
+    if (st) return fail(c, st, "%s", err.c_str());
+    if (n_sel != k) return fail(c, VADX_E_ARG, "selection returned %lld of %d", (long long)n_sel, k);
+    HIP_TRY(c, launch_rank_sort(score, cand, k, idx, val, c->stream));
     return VADX_OK;
 }
 

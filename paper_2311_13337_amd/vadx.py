@@ -33,7 +33,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
            "vadx_analysis_ws_bytes", "vadx_analyze_series", "vadx_analyze",
-           "vadx_analysis_kernel_time", "vadx_set_reference_fc", "vadx_top_k",
+           "vadx_analysis_kernel_time", "vadx_set_reference_fc", "vadx_top_k", "vadx_top_k_noalloc",
            "vadx_set_instance_param", "vadx_bold_defaults", "vadx_bold_series", "vadx_bold")
 INSTANCE_PARAMS = {"w_noise": 0, "tau_w_e": 1, "cF_ee": 2, "cF_ei": 3, "cF_ie": 4, "cF_ii": 5}
 ANALYSIS_KERNELS = ("an_transpose_kernel", "an_welch_kernel", "an_hilbert_kernel", "an_pli_kernel",
@@ -163,6 +163,7 @@ def lib():
             "vadx_analysis_kernel_time": (st, [vp, vp, vp]),
             "vadx_set_reference_fc": (st, [vp, C.c_int32, vp]),
             "vadx_top_k": (st, [vp, vp, C.c_int64, C.c_int32, vp, vp]),
+            "vadx_top_k_noalloc": (st, [vp, vp, C.c_int64, C.c_int32, vp, vp]),
             "vadx_set_instance_param": (st, [vp, C.c_int32, C.c_int64, vp]),
             "vadx_bold_defaults": (st, [P(vadx_bold_cfg)]),
             "vadx_bold_series": (st, [vp, vp, C.c_int64, C.c_int32, C.c_int64, C.c_double,
@@ -370,6 +371,13 @@ class Context:
         self._check(lib().vadx_top_k(self.h, C.c_void_p(score.data_ptr()), score.numel(), k,
                                      C.c_void_p(idx.data_ptr()), C.c_void_p(val.data_ptr())))
         return idx[:k], val[:k]
+
+    def vadx_top_k_noalloc(self, score, k: int, idx, val=None):
+        """As vadx_top_k into caller-given device tensors idx (int64, >= k) and
+        val (float32, nullable); the library allocates nothing."""
+        self._check(lib().vadx_top_k_noalloc(self.h, C.c_void_p(score.data_ptr()), score.numel(), k,
+                                             C.c_void_p(idx.data_ptr()),
+                                             C.c_void_p(val.data_ptr()) if val is not None else None))
 
     def vadx_bold_series(self, samples, n_samples: int, n: int, period_ms: float,
                          cfg: "vadx_bold_cfg" = None):
