@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--waves-per-simd", type=int, default=2, choices=[2, 3],
                    help="register budget of the integration kernel when not autotuning")
     p.add_argument("--wg-instances", type=int, default=0,
-                   help="instances per workgroup when not autotuning (0 = as many as fit 512 lanes)")
+                   help="instances per workgroup when not autotuning (0 = as many as fit the lane budget)")
     p.add_argument("--item-steps", type=int, default=0,
                    help="queue item length with --no-autotune (0 = 1000)")
     p.add_argument("--tune-steps", type=int, default=16000,

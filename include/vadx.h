@@ -240,7 +240,7 @@ vadx_status vadx_set_launch(vadx_ctx *ctx, int32_t mode, int32_t wg_instances, i
 
 /* Lane budget of the workgroups holding instances of n_regions regions: each
  * packs floor(lanes / n_regions) instances (at least one) on consecutive
- * lanes. lanes in [64, 512] sets it, 0 returns it to the default (512), -1
+ * lanes. lanes in [64, 512] sets it, 0 returns it to the default (256), -1
  * leaves it; *current (nullable) receives the budget in effect. Takes effect
  * at the next vadx_plan; results do not depend on it. */
 vadx_status vadx_class_lanes(vadx_ctx *ctx, int32_t n_regions, int32_t lanes, int32_t *current);
@@ -254,7 +254,7 @@ vadx_status vadx_set_waves_per_simd(vadx_ctx *ctx, int32_t waves);
 /* Autotuner of the launch shape for the current batch: times trial runs of
  * trial_steps steps (0 = 2000; no samples) of `run` in `ws` (device, at least
  * the size vadx_plan gave for `run`; its contents are overwritten) of the
- * persistent launch. Starting from 512-lane budgets with 2 waves per SIMD
+ * persistent launch. Starting from 256-lane budgets with 2 waves per SIMD
  * and 1000-step items, it tries each region-count class's lane budgets in
  * turn (64..512 lanes, one per distinct instance count per workgroup; the
  * other classes at their best so far), then 2 or 3 waves per SIMD with items

@@ -125,6 +125,8 @@ VADX_HD float lg2(float x)
 VADX_HD double sqr(double x) { return __builtin_sqrt(x); }
 VADX_HD double maxd_(double a, double b) { return __builtin_fmax(a, b); }
 VADX_HD double mind_(double a, double b) { return __builtin_fmin(a, b); }
+VADX_HD float maxd_(float a, float b) { return __builtin_fmaxf(a, b); }
+VADX_HD float mind_(float a, float b) { return __builtin_fminf(a, b); }
 VADX_HD bool finite_(float x) { return __builtin_isfinite(x); }
 VADX_HD float fmaf_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 VADX_HD float absf_(float x) { return __builtin_fabsf(x); }
@@ -487,6 +489,11 @@ template <class S> VADX_HD S clampv(S x, S lo, S hi, bool &hit)
     hit = hit || (y != x);
     return y;
 }
+// Below C_ei^2 < C_ee C_ii * proj_skip (each side rounded) |C_ei| is below
+// sqrt(C_ee C_ii) in any rounding: 1 - 2^-40 in double, 1 - 1e-5 in single
+// precision (margins of many ulps over the products' and the root's rounding).
+VADX_HD double proj_skip(double) { return 0.99999999999909051; }
+VADX_HD float proj_skip(float) { return 0.99999f; }
 template <class S> VADX_HD bool project(const KModel &M, S X[8])
 {
     bool hit = false;
@@ -500,7 +507,7 @@ template <class S> VADX_HD bool project(const KModel &M, S X[8])
     // |C_ei| < sqrt(C_ee C_ii) in any rounding, so the clamp would leave C_ei
     // unchanged and flag nothing.
     const S p = X[2] * X[4];
-    if (X[3] * X[3] >= p * S(0.99999999999909051)) {
+    if (X[3] * X[3] >= p * proj_skip(S(0))) {
         S cb = sqr(p);
         X[3] = clampv(X[3], -cb, cb, hit);
     }
@@ -520,7 +527,6 @@ VADX_HD uint32_t step_region(const KModel &M, int integrator, S dt, S X[8], T c,
                              const InstModel<T> &P, S gdw)
 {
     T xf[8], f0[8], f1[8];
-    S Xt[8];
     for (int q = 0; q < 8; ++q) xf[q] = T(X[q]);
     drift<VAR>(M, xf, c, P, f0);
     if (integrator == 1) {
@@ -529,10 +535,11 @@ VADX_HD uint32_t step_region(const KModel &M, int integrator, S dt, S X[8], T c,
         X[7] = X[7] + gdw;
         return nf | (project(M, X) ? kStepClamp : 0u);
     }
-    for (int q = 0; q < 8; ++q) Xt[q] = X[q] + dt * S(f0[q]);
-    Xt[7] = Xt[7] + gdw;
-    bool hit = project(M, Xt);
-    for (int q = 0; q < 8; ++q) xf[q] = T(Xt[q]);
+    // predictor in single precision: it feeds only the second drift, which
+    // takes single-precision inputs anyway
+    for (int q = 0; q < 8; ++q) xf[q] = fmaf_(T(dt), f0[q], xf[q]);
+    xf[7] = xf[7] + T(gdw);
+    bool hit = project(M, xf);
     drift<VAR>(M, xf, c, P, f1);
     const uint32_t nf = finite_((f0[0] + f0[1]) + (f1[0] + f1[1])) ? 0u : kStepNonfinite;
     const S hdt = S(0.5) * dt;

@@ -46,6 +46,10 @@ inline CF selectf(bool c, CF a, CF b) { return c ? a : b; }
 inline CF maxf_(CF a, CF b) { CF::flop(1); return mk<float>(std::fmax(a.v, b.v)); }
 inline CD maxd_(CD a, CD b) { CD::flop(1); return mk<double>(std::fmax(a.v, b.v)); }
 inline CD mind_(CD a, CD b) { CD::flop(1); return mk<double>(std::fmin(a.v, b.v)); }
+inline CF maxd_(CF a, CF b) { CF::flop(1); return mk<float>(std::fmax(a.v, b.v)); }
+inline CF mind_(CF a, CF b) { CF::flop(1); return mk<float>(std::fmin(a.v, b.v)); }
+inline CD proj_skip(CD) { return CD(0.99999999999909051); }
+inline CF proj_skip(CF) { return CF(0.99999); }
 inline bool finite_(CF x) { return std::isfinite(x.v); }
 template <class U> bool operator!=(Cnt<U> a, Cnt<U> b) { return a.v != b.v; }
 } // namespace vadx

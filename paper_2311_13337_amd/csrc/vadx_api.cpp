@@ -139,7 +139,7 @@ struct vadx_ctx {
     void *g_ws = nullptr;
     uint64_t g_epoch = 0, plan_epoch = 0;
     int wg_instances_override = 0;
-    int wg_lanes = 512;                  // lane budget per workgroup (autotuned)
+    int wg_lanes = 256;                  // lane budget per workgroup (autotuned)
     std::map<int, int> class_lanes;      // lane budget per region count (autotuned; else wg_lanes)
     int occ = 2;                         // waves per SIMD of the persistent kernel (autotuned)
     int item_steps = 1000;
@@ -1078,7 +1078,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     c->timing = false;
     // the region-count classes of the batch
     std::map<int, int> lanes;
-    for (int32_t ci : c->conn_of) lanes[c->conns[ci].n] = 512;
+    for (int32_t ci : c->conn_of) lanes[c->conns[ci].n] = 256;
     vadx_status result = VADX_OK;
     std::map<int, int> best_l = lanes;
     int best_i = 1000, best_w = 2;
@@ -1153,7 +1153,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         }
         // the register budget and the item length together, at the chosen lane budgets
         for (int w : {2, 3})
-            for (int it : {500, 1000, 2000, 4000, 8000}) {
+            for (int it : {500, 1000, 2000, 3000, 4000, 8000}) {
                 if (result) break;
                 if (w == 2 && it == 1000) continue;
                 result = trial(best_l, it, w, &ms);

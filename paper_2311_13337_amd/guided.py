@@ -48,6 +48,8 @@ class GuidedConfig:
     train_seed: int = 4
     top_frac: float = 0.05             # refined by predicted transition gradient
     audit_frac: float = 0.01           # random audit of the rest
+    min_audit: int = 2000              # at least this many audit points (a 5 % exceed fraction
+                                       # then has a binomial standard error below 0.5 points)
     audit_seed: int = 7
     run: inputs.RunConfig = inputs.RUN_UNIFORM
     batch: int = 1024
@@ -165,14 +167,21 @@ def train_error_net(net, X, Y, cfg: GuidedConfig, log=print):
     return err_net, info
 
 
+def audit_fraction(cfg: GuidedConfig, n: int) -> float:
+    """The audit's sampling fraction: cfg.audit_frac, raised on small grids so
+    that the audit holds about cfg.min_audit points."""
+    return float(min(1.0, max(cfg.audit_frac, cfg.min_audit / max(n, 1))))
+
+
 def select(net, score, k, cfg: GuidedConfig):
     """Indices of the k largest scores plus the audit sample, and audit flags."""
     import torch
     n = score.numel()
-    cap = k + int(n * cfg.audit_frac * 1.5) + 1024
+    frac = audit_fraction(cfg, n)
+    cap = k + int(n * frac * 1.5) + 1024
     sel = torch.empty(cap, dtype=torch.int64, device=score.device)
     aud = torch.empty(cap, dtype=torch.uint8, device=score.device)
-    m = net.select(score, k, cfg.audit_frac, cfg.audit_seed, sel, aud)
+    m = net.select(score, k, frac, cfg.audit_seed, sel, aud)
     return sel[:m].cpu().numpy(), aud[:m].cpu().numpy().astype(bool)
 
 
@@ -220,7 +229,7 @@ def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False
     idx, is_aud = select(net, score, k1, cfg)
     t_select = time.perf_counter() - t0
     log(f"[guided] screened {n} points in {t_screen:.2f} s; refining {len(idx)} "
-        f"({int((~is_aud).sum())} by gradient, {int(is_aud.sum())} audit)")
+        f"({int((~is_aud).sum())} by score, {int(is_aud.sum())} audit)")
     Yref, fref, t_refine = sim(grid.subset(idx), idx, "refinement")
     k2 = k1
     if cfg.adaptive and is_aud.any():
@@ -282,4 +291,5 @@ def guided_sweep(cfg: GuidedConfig = GuidedConfig(), log=print, plain_full=False
     }
     res["passes_err_bound"] = res["fc_mean_err"]["p95"] < cfg.err_bound
     return res, {"guided": guided, "pred": Yhat, "idx": idx, "check": chk, "plain": Yplain,
-                 "grid": G, "train_X": _points(train), "train_Y": Ytrain}
+                 "grid": G, "train_X": _points(train), "train_Y": Ytrain,
+                 "score": score.cpu().numpy()}

@@ -543,7 +543,7 @@ def test_autotuner_choice_cached_and_result_unchanged(tmp_path):
     sw.plan(vadx.make_run(cfg))
     cache = str(tmp_path / "tune.json")
     lanes, items, waves = sw.autotune(cache, trial_steps=200)
-    assert 200 <= lanes <= 512 and lanes % 64 == 0 and items in (500, 1000, 2000, 4000, 8000)
+    assert 200 <= lanes <= 512 and lanes % 64 == 0 and items in (500, 1000, 2000, 3000, 4000, 8000)
     assert waves in (2, 3)
     entries = json.load(open(cache))
     assert len(entries) == 1
