@@ -39,6 +39,9 @@ def parse():
                    help="register budget of the integration kernel when not autotuning")
     p.add_argument("--wg-instances", type=int, default=0,
                    help="instances per workgroup when not autotuning (0 = as many as fit the lane budget)")
+    p.add_argument("--lanes", type=int, default=0,
+                   help="lane budget of every region-count class when not autotuning (0 = the "
+                        "library's default, 256)")
     p.add_argument("--item-steps", type=int, default=0,
                    help="queue item length with --no-autotune (0 = 1000)")
     p.add_argument("--tune-steps", type=int, default=16000,
@@ -133,8 +136,12 @@ def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
     sw.plan(run)
     sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
     sw.ctx.vadx_set_launch(0, args.wg_instances, args.item_steps)
+    if args.lanes:
+        for c in conns:
+            sw.ctx.vadx_class_lanes(int(c.n), args.lanes)
     sw.plan(run)
     shape = {"instances_per_workgroup": args.wg_instances or "max",
+             "lanes": args.lanes or "default",
              "item_steps": args.item_steps or 1000,
              "waves_per_simd": args.waves_per_simd, "autotuned": False}
     if not args.no_autotune:
@@ -439,8 +446,8 @@ def guided_line(record_path, write_record=False):
             "grid_points": res["grid_points"], "check_points": res["check_points"],
             "guided_digest": digest,
             "workload": "32^4 grid over S [0,0.5] x b_e [0,120] x a_e [0,8] x v [1,10], 10-s runs; "
-                        "32768 training runs; top 5 % by surrogate gradient + 1 % audit, then "
-                        "audit-driven refinement"}
+                        "32768 training runs; top 5 % by the error network's prediction + 1 % audit, "
+                        "then audit-driven refinement down that order"}
     if rec:
         line["full_grid"] = {k: rec[k] for k in ("fc_mean_err_full_grid", "active_fraction", "plain_s")}
         line["fc_mean_err_p95"] = round(rec["fc_mean_err_full_grid"]["p95"], 4)

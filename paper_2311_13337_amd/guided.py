@@ -54,9 +54,9 @@ class GuidedConfig:
     run: inputs.RunConfig = inputs.RUN_UNIFORM
     batch: int = 1024
     lr: float = 1e-3
-    max_epochs: int = 400
+    max_epochs: int = 4000
     eval_every: int = 5
-    patience: int = 40                 # epochs without a better validation loss
+    patience: int = 400                # epochs without a better validation loss
     val_frac: float = 0.1
     split_seed: int = 0
     init_seed: int = 0
