@@ -245,26 +245,42 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
 #pragma unroll
             for (int b = 0; b < B; ++b) cb[b] = 0.f;
             if (nb == B) {
-                // kGatherEdges edges per round: their index and history loads
-                // are all in flight before the first multiply-add, so a row
-                // costs a few memory round trips instead of two per edge. The
-                // sums still run over the edges in row order. A round past the
-                // row's end reloads the row's first edge and adds nothing.
+                // kGatherEdges edges per round, without branches: the round's
+                // history loads are all in flight before its first multiply-add,
+                // and the next round's edge indices and weights are loaded while
+                // they are, so a round costs one memory round trip. Past the
+                // row's end a round re-reads the row's last edge with weight 0.
+                // The sums run over the edges in row order. Offsets stay in 32
+                // bits: j < 512 regions and ring rows under 2^20 + 64 slots, so
+                // j * Dp fits the 24-bit multiplier and the offset an int.
                 constexpr int U = kGatherEdges<B>;
-                for (int e0 = row_b; e0 < row_e; e0 += U) {
+                // the row bounds pass through an empty asm so that the first
+                // round's addresses are formed here, each block, instead of
+                // being hoisted out of the block loop and kept (spilled) across
+                // the steps
+                int rb = row_b, re = row_e;
+                asm volatile("" : "+v"(rb), "+v"(re));
+                const int last = re - 1;
+                int32_t pk[U];
+                float w[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    // an empty row loads nothing (its first index may be the
+                    // table's end)
+                    const int e = min(rb + u, last);
+                    pk[u] = rb < re ? prow[e] : 0;
+                    w[u] = rb < re ? wrow[e] : 0.f;
+                }
+                for (int e0 = rb; e0 < re; e0 += U) {
                     const float *h[U];
-                    float w[U];
-                    bool ok[U];
+                    float wc[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        ok[u] = e0 + u < row_e;
-                        const int e = ok[u] ? e0 + u : row_b;
-                        const int32_t pk = prow[e];
-                        const int j = pk >> 20, d = pk & 0xFFFFF;
-                        w[u] = wrow[e];
+                        const int j = pk[u] >> 20, d = pk[u] & 0xFFFFF;
                         int s0 = nm - d;
                         s0 += (s0 < 0) ? D : 0;
-                        h[u] = ring + (int64_t)j * Dp + s0;
+                        h[u] = ring + (__umul24((uint32_t)j, (uint32_t)Dp) + (uint32_t)s0);
+                        wc[u] = e0 + u < re ? w[u] : 0.f;
                     }
                     float hv[U][B];
 #pragma unroll
@@ -272,11 +288,17 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
 #pragma unroll
                         for (int b = 0; b < B; ++b) hv[u][b] = h[u][b];
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (ok[u]) {
+                    for (int u = 0; u < U; ++u) {
+                        const int e = min(e0 + U + u, last);
+                        pk[u] = prow[e];
+                        w[u] = wrow[e];
+                    }
+                    // keep those loads here, ahead of the waits for the histories
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                            for (int b = 0; b < B; ++b) cb[b] = fmaf(w[u], hv[u][b], cb[b]);
-                        }
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int b = 0; b < B; ++b) cb[b] = fmaf(wc[u], hv[u][b], cb[b]);
                 }
             } else {
                 for (int e = row_b; e < row_e; ++e) {
@@ -294,7 +316,6 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
 #pragma unroll
             for (int b = 0; b < B; ++b) cbuf[b * nthr + tid] = S * cb[b];
 
-            int wm = nm;
             const bool tracing = trace != nullptr && n0 < a.n_trace_steps;
             for (int b = 0; b < nb; ++b) {
                 const int n = (int)(n0 + b);
@@ -305,12 +326,10 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                 const float c = cbuf[b * nthr + tid];
                 fl |= step_region<VAR>(M, a.integrator, a.dt, X, c, P,
                                        a.gdw_scale * (double)z);
-                // history of E: slot (n + 1) mod D, and its mirror
-                wm += 1;
-                wm -= (wm >= D) ? D : 0;
+                // the new E waits in this step's coupling slot, which is free
+                // now, and goes to the history ring at the end of the block
                 const float e1 = (float)X[0];
-                myrow[wm] = e1;
-                if (wm < B - 1) myrow[D + wm] = e1;
+                cbuf[b * nthr + tid] = e1;
                 // time average
                 acc += e1;
                 if (++tc == tavg) {
@@ -324,6 +343,32 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                     float *tr = trace + (int64_t)n * 8 * I.n + k;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) tr[q * I.n] = (float)X[q];
+                }
+            }
+            // history of E for steps n0+1 .. n0+nb: slots (n0 + 1 + b) mod D, and
+            // the mirrors D + t of slots t < B - 1, written as one run per lane
+            // (nothing reads them before the block is published)
+            int t0 = nm + 1;
+            t0 -= (t0 >= D) ? D : 0;
+            if (nb == B && t0 + B <= D) {
+                float eb[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) eb[b] = cbuf[b * nthr + tid];
+#pragma unroll
+                for (int b = 0; b < B; ++b) myrow[t0 + b] = eb[b];
+                if (t0 < B - 1) {
+#pragma unroll
+                    for (int b = 0; b < B - 1; ++b)
+                        if (t0 + b < B - 1) myrow[D + t0 + b] = eb[b];
+                }
+            } else {
+                int t = t0;
+                for (int b = 0; b < nb; ++b) {
+                    const float e = cbuf[b * nthr + tid];
+                    myrow[t] = e;
+                    if (t < B - 1) myrow[D + t] = e;
+                    t += 1;
+                    t -= (t >= D) ? D : 0;
                 }
             }
             nm += nb;
