@@ -44,6 +44,8 @@ def parse():
                         "library's default, 256)")
     p.add_argument("--item-steps", type=int, default=0,
                    help="queue item length with --no-autotune (0 = 1000)")
+    p.add_argument("--wave-slack", type=int, default=0, choices=[0, 1],
+                   help="wave slack of the integration when not autotuning")
     p.add_argument("--tune-steps", type=int, default=16000,
                    help="steps of each autotuner trial run")
     p.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "vadx_tune.json"))
@@ -136,6 +138,7 @@ def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
     sw.plan(run)
     sw.ctx.vadx_set_waves_per_simd(args.waves_per_simd)
     sw.ctx.vadx_set_launch(0, args.wg_instances, args.item_steps)
+    sw.ctx.vadx_wave_slack(args.wave_slack)
     if args.lanes:
         for c in conns:
             sw.ctx.vadx_class_lanes(int(c.n), args.lanes)
@@ -151,6 +154,7 @@ def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
     ctx = sw.ctx
     shape.update(ctx.vadx_launch_info())
     shape["class_lanes"] = {int(c.n): ctx.vadx_class_lanes(int(c.n)) for c in conns}
+    shape["wave_slack"] = ctx.vadx_wave_slack()
     for _ in range(warmup):
         sw.integrate()
     torch.cuda.synchronize()

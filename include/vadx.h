@@ -246,24 +246,40 @@ vadx_status vadx_set_launch(vadx_ctx *ctx, int32_t mode, int32_t wg_instances, i
 vadx_status vadx_class_lanes(vadx_ctx *ctx, int32_t n_regions, int32_t lanes, int32_t *current);
 
 /* Register budget of the persistent integration kernel in waves per SIMD: 2
- * (one 512-lane or two 256-lane workgroups per CU, no spills; the default) or
- * 3 (three 256-lane workgroups per CU; a few spills outside the step loop).
- * Takes effect at the next vadx_plan; results do not depend on it. */
+ * (one 512-lane or two 256-lane workgroups per CU; the default) or 3 (three
+ * 256-lane workgroups per CU; registers spill inside the step loop, measured
+ * about half as fast on 68-region sweeps). Takes effect at the next
+ * vadx_plan; results do not depend on it. */
 vadx_status vadx_set_waves_per_simd(vadx_ctx *ctx, int32_t waves);
+
+/* Wave slack of the integration. The waves that hold an instance's regions
+ * exchange delayed rates through its history ring once per block of steps.
+ * 0 (the default): blocks of up to d_min + 1 steps (d_min: the instance's
+ * shortest delay in steps), each reading what the other waves published by
+ * the end of the previous block. 1: where half that bound still allows a
+ * block of at least 12 steps, blocks of at most (d_min + 1) / 2 steps that
+ * read only what was published two blocks back, so a wave may run one block
+ * further ahead of the waves it shares instances with (the ring grows by one
+ * block); other instances keep slack 0. slack in {0, 1} sets it, -1 leaves it;
+ * *current (nullable) receives the setting in effect. Takes effect at the next
+ * vadx_plan; results do not depend on it (the same sums in the same order). */
+vadx_status vadx_wave_slack(vadx_ctx *ctx, int32_t slack, int32_t *current);
 
 /* Autotuner of the launch shape for the current batch: times trial runs of
  * trial_steps steps (0 = 2000; no samples) of `run` in `ws` (device, at least
  * the size vadx_plan gave for `run`; its contents are overwritten) of the
  * persistent launch. Starting from 256-lane budgets with 2 waves per SIMD
- * and 1000-step items, it tries each region-count class's lane budgets in
- * turn (64..512 lanes, one per distinct instance count per workgroup; the
- * other classes at their best so far), then 2 or 3 waves per SIMD with items
- * of 500..8000 steps at the chosen budgets, and keeps the fastest. With a
- * cache_path (nullable) the choice is read from / added to that JSON file,
- * keyed by device, longest block length and the region-count mix; a cached
- * choice is applied without trials. *lanes (the widest class budget),
- * *item_steps, *waves (nullable) receive the choice; vadx_class_lanes reads
- * each class's budget. Call vadx_plan again before vadx_integrate. */
+ * and 1000-step items, for wave slack 0 and 1 it tries each region-count
+ * class's lane budgets in turn (64..512 lanes, one per distinct instance count
+ * per workgroup; the other classes at their best so far), keeps the faster
+ * slack, then tries 2 or 3 waves per SIMD with items of 500..8000 steps at
+ * the chosen budgets, and keeps the fastest. With a cache_path (nullable) the
+ * choice is read from / added to that JSON file, keyed by device, longest
+ * block length (without slack) and the region-count mix; a cached choice is
+ * applied without trials. *lanes (the widest class budget), *item_steps,
+ * *waves (nullable) receive the choice; vadx_class_lanes and vadx_wave_slack
+ * read the class budgets and the slack. Call vadx_plan again before
+ * vadx_integrate. */
 vadx_status vadx_autotune(vadx_ctx *ctx, const vadx_run *run, void *ws, size_t ws_bytes,
                           const char *cache_path, int32_t trial_steps, int32_t *lanes,
                           int32_t *item_steps, int32_t *waves);

@@ -150,10 +150,11 @@ __device__ __forceinline__ void wait_waves(const int *wdone, int lo, int hi, int
 // starts with a workgroup barrier. Inside, waves synchronise only with the
 // waves that share an instance with them: before the gather of block m a
 // wave waits until those waves have written the histories of block m-1
+// (m-2 for groups with lag 1, whose blocks are at most (d_min + 1) / 2 steps)
 // (counters in LDS, `wdone`), so waves of different instances drift apart
-// by up to a block instead of meeting at a barrier after every block. The
-// ring depth (d_max + B + 1) keeps a block's writes clear of every slot a
-// wave one block behind still reads.
+// by up to 1 + lag blocks instead of meeting at a barrier after every block.
+// The ring depth (d_max + (1 + lag) B + 1) keeps a block's writes clear of
+// every slot a wave that far behind still reads.
 //
 template <int B, int VAR>
 __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const GroupDev g,
@@ -237,7 +238,8 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
     int m = 0;   // blocks published by this wave
     for (int64_t n0 = n_begin; n0 < n_end && wave_live; n0 += B, ++m) {
         const int nb = (int)((n_end - n0) < B ? (n_end - n0) : B);
-        if (m > 0) wait_waves(wdone, wlo, whi, wave, m, a.status, a.wait_spins);
+        // block m reads rates published by the end of block m - 1 - lag
+        if (m > g.lag) wait_waves(wdone, wlo, whi, wave, m - g.lag, a.status, a.wait_spins);
         if (active) {
             // coupling of steps n0 .. n0+nb-1: S sum_j W_kj H_j[n - d_kj], in the
             // fixed (ascending j) order of the CSR row
@@ -407,6 +409,7 @@ __device__ __forceinline__ void integrate_group_any(const IntegrateArgs &a, cons
     case 2: integrate_group<2, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
     case 4: integrate_group<4, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
     case 8: integrate_group<8, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
+    case 12: integrate_group<12, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
     case 16: integrate_group<16, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
     case 24: integrate_group<24, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
     default: integrate_group<32, VAR>(a, g, n_begin, n_end, cbuf, wdone); break;
@@ -533,6 +536,7 @@ static hipError_t launch_integrate_v(const IntegrateArgs &a, int n_groups, int b
     case 2: return launch_integrate_b<2, VAR>(a, n_groups, block_threads, s);
     case 4: return launch_integrate_b<4, VAR>(a, n_groups, block_threads, s);
     case 8: return launch_integrate_b<8, VAR>(a, n_groups, block_threads, s);
+    case 12: return launch_integrate_b<12, VAR>(a, n_groups, block_threads, s);
     case 16: return launch_integrate_b<16, VAR>(a, n_groups, block_threads, s);
     case 24: return launch_integrate_b<24, VAR>(a, n_groups, block_threads, s);
     case 32: return launch_integrate_b<32, VAR>(a, n_groups, block_threads, s);

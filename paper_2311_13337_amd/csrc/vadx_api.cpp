@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -142,6 +143,7 @@ struct vadx_ctx {
     int wg_lanes = 256;                  // lane budget per workgroup (autotuned)
     std::map<int, int> class_lanes;      // lane budget per region count (autotuned; else wg_lanes)
     int occ = 2;                         // waves per SIMD of the persistent kernel (autotuned)
+    int slack = 0;                       // half-length blocks with one block of lag where they stay long (autotuned)
     int item_steps = 1000;
     int cus = 0;
 };
@@ -454,23 +456,31 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     const int64_t ns = (r->n_steps - r->transient_steps) / r->tavg_steps;
     // ring depths and block lengths: a block of B steps reads histories up to
     // B-1 steps ahead of its first step, so B <= d_min + 1 (each instance's own
-    // shortest delay); rings hold d_max + B + 1 slots so a block's writes never
-    // overwrite a value that a lane of the same block still has to read.
+    // shortest delay) lets it read what the waves of its instance published
+    // by the end of the previous block. With lag 1 (wave slack, where the half
+    // length is still >= kSlackMinBlock steps) B <= (d_min + 1) / 2, so a block
+    // reads only what was published two blocks back and a wave may run a block
+    // further ahead of the others. Rings hold d_max + (1 + lag) B + 1 slots: the
+    // furthest a wave can write ahead of the oldest slot another wave of its
+    // instance still has to read.
     std::vector<int64_t> dmax(ni);
-    std::vector<int> blk(ni);
+    std::vector<int> blk(ni), lag(ni);
     int bmax = 1;
     for (int64_t i = 0; i < ni; ++i) {
         const HostConn &hc = c->conns[c->conn_of[i]];
         const int64_t dm = hc.nnz ? host_delay(hc.len_min, c->v[i], r->dt_ms) : 1;
         dmax[i] = hc.nnz ? host_delay(hc.len_max, c->v[i], r->dt_ms) : 1;
-        if (dmax[i] >= (1 << 20) - kMaxBlock - 2)
+        if (dmax[i] >= (1 << 20) - 2 * kMaxBlock - 2)
             return fail(c, VADX_E_UNSUPPORTED, "delay of %lld steps too long", (long long)dmax[i]);
-        // the longest of 1, 2, 4, 8, 16, 24, 32 steps within the bound
-        int B = 1;
-        for (int cand : {2, 4, 8, 16, 24, 32})
+        // the longest of 1, 2, 4, 8, 12, 16, 24, 32 steps within the bound
+        int B = 1, Bh = 1;
+        for (int cand : {2, 4, 8, 12, 16, 24, 32}) {
             if (cand <= kMaxBlock && cand <= dm + 1) B = cand;
-        blk[i] = B;
-        bmax = std::max(bmax, B);
+            if (cand <= kMaxBlock && 2 * cand <= dm + 1) Bh = cand;
+        }
+        lag[i] = (c->slack && Bh >= kSlackMinBlock) ? 1 : 0;
+        blk[i] = lag[i] ? Bh : B;
+        bmax = std::max(bmax, blk[i]);
     }
     c->block = bmax;
     // launch and item lengths are multiples of every block length present
@@ -505,6 +515,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     for (int64_t i = 0; i < ni; ++i) order[i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         if (blk[a] != blk[b]) return blk[a] > blk[b];
+        if (lag[a] != lag[b]) return lag[a] < lag[b];
         if (c->conn_of[a] != c->conn_of[b]) return c->conn_of[a] < c->conn_of[b];
         return dmax[a] < dmax[b];
     });
@@ -513,17 +524,19 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     c->classes.clear();
     for (int64_t s = 0; s < ni;) {
         const int32_t cid = c->conn_of[order[s]];
-        const int B = blk[order[s]];
+        const int B = blk[order[s]], L = lag[order[s]];
         const int n = c->conns[cid].n;
         const auto cl = c->class_lanes.find(n);
         int per = std::max(1, (cl != c->class_lanes.end() ? cl->second : c->wg_lanes) / n);
         if (c->wg_instances_override > 0) per = std::min(per, c->wg_instances_override);
         int64_t e = s;
-        while (e < ni && e - s < per && c->conn_of[order[e]] == cid && blk[order[e]] == B) ++e;
+        while (e < ni && e - s < per && c->conn_of[order[e]] == cid && blk[order[e]] == B &&
+               lag[order[e]] == L)
+            ++e;
         if (c->classes.empty() || c->classes.back().block != B)
             c->classes.push_back(BlockClass{B, (int32_t)c->h_groups.size(), 0, 64});
         BlockClass &bc = c->classes.back();
-        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, B});
+        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, B, L});
         bc.n_groups += 1;
         bc.threads = std::max(bc.threads, (int)(((e - s) * n + 63) / 64 * 64));
         s = e;
@@ -547,7 +560,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         d.cF[2] = (float)ip(VADX_P_CF_IE, c->model.cF_ie);
         d.cF[3] = (float)ip(VADX_P_CF_II, c->model.cF_ii);
         d.n = hc.n;
-        d.D = (int32_t)(dmax[i] + blk[i] + 1);
+        d.D = (int32_t)(dmax[i] + (1 + lag[i]) * blk[i] + 1);
         d.Dp = d.D + blk[i] - 1;
         d.conn = c->conn_of[i];
         d.id = c->noise_key[(size_t)i];
@@ -777,6 +790,18 @@ vadx_status vadx_set_waves_per_simd(vadx_ctx *c, int32_t waves)
     return VADX_OK;
 }
 
+vadx_status vadx_wave_slack(vadx_ctx *c, int32_t slack, int32_t *current)
+{
+    if (!c) return VADX_E_ARG;
+    if (slack < -1 || slack > 1) return fail(c, VADX_E_ARG, "wave slack must be 0, 1 or -1");
+    if (slack >= 0 && slack != c->slack) {
+        c->slack = slack;
+        c->planned = false;
+    }
+    if (current) *current = c->slack;
+    return VADX_OK;
+}
+
 vadx_status vadx_launch_info(vadx_ctx *c, int32_t *groups, int32_t *block_threads,
                              int32_t *grid, int32_t *steps_per_block)
 {
@@ -998,7 +1023,7 @@ static bool lanes_parse(const std::string &t, std::map<int, int> *m)
 }
 
 static bool tune_lookup(const char *path, const std::string &key, std::map<int, int> *lanes, int *items,
-                        int *occ)
+                        int *occ, int *slack)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -1015,9 +1040,15 @@ static bool tune_lookup(const char *path, const std::string &key, std::map<int, 
         if (l1 != std::string::npos && lanes_parse(line.substr(l0, l1 - l0), &m) &&
             std::sscanf(line.c_str() + pi + 13, "%d", &it) == 1 &&
             std::sscanf(line.c_str() + pw + 17, "%d", &w) == 1 && it > 0 && w >= 2 && w <= 3) {
+            // entries written before the slack setting existed were tuned without it
+            int sl = 0;
+            const size_t ps = line.find("\"wave_slack\":", at);
+            if (ps != std::string::npos && (std::sscanf(line.c_str() + ps + 13, "%d", &sl) != 1 || sl < 0 || sl > 1))
+                continue;
             *lanes = m;
             *items = it;
             *occ = w;
+            *slack = sl;
             return true;
         }
     }
@@ -1025,7 +1056,7 @@ static bool tune_lookup(const char *path, const std::string &key, std::map<int, 
 }
 
 static void tune_store(const char *path, const std::string &key, const std::map<int, int> &lanes,
-                       int items, int occ, double ms)
+                       int items, int occ, int slack, double ms)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -1041,8 +1072,8 @@ static void tune_store(const char *path, const std::string &key, const std::map<
     char buf[640];
     std::snprintf(buf, sizeof(buf),
                   "  \"%s\": {\"class_lanes\": \"%s\", \"item_steps\": %d, \"waves_per_simd\": %d, "
-                  "\"trial_ms\": %.3f}",
-                  key.c_str(), lanes_str(lanes).c_str(), items, occ, ms);
+                  "\"wave_slack\": %d, \"trial_ms\": %.3f}",
+                  key.c_str(), lanes_str(lanes).c_str(), items, occ, slack, ms);
     keep.push_back(buf);
     std::ofstream o(path, std::ios::trunc);
     o << "{\n";
@@ -1068,7 +1099,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     t.chunk_steps = 0;
     size_t need = 0;
     const int saved_mode = c->launch_mode, saved_override = c->wg_instances_override;
-    const int saved_occ = c->occ;
+    const int saved_occ = c->occ, saved_slack = c->slack;
     const bool saved_graph = c->use_graph, saved_timing = c->timing;
     std::vector<int64_t> saved_traced = c->traced;
     c->traced.clear();
@@ -1081,11 +1112,12 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     for (int32_t ci : c->conn_of) lanes[c->conns[ci].n] = 256;
     vadx_status result = VADX_OK;
     std::map<int, int> best_l = lanes;
-    int best_i = 1000, best_w = 2;
+    int best_i = 1000, best_w = 2, best_s = 0;
     double best_ms = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto restore = [&]() {
         c->occ = saved_occ;
+        c->slack = saved_slack;
         c->launch_mode = saved_mode;
         c->wg_instances_override = saved_override;
         c->use_graph = saved_graph;
@@ -1095,14 +1127,20 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    auto trial = [&](const std::map<int, int> &l, int items, int occ, double *ms) -> vadx_status {
+    auto trial = [&](const std::map<int, int> &l, int items, int occ, int slack, double *ms) -> vadx_status {
         c->class_lanes = l;
         c->item_steps = items;
         c->occ = occ;
+        c->slack = slack;
         c->planned = false;
         vadx_status st = vadx_plan(c, &t, &need);
         if (st) return st;
-        if (need > ws_bytes) return fail(c, VADX_E_OOM, "workspace too small for the trial runs");
+        // a shape whose plan needs more workspace than given (deeper rings
+        // under wave slack) is left out
+        if (need > ws_bytes) {
+            *ms = std::numeric_limits<double>::infinity();
+            return VADX_OK;
+        }
         HIP_TRY(c, hipEventRecord(e0, c->stream));
         st = enqueue_run(c, &t, ws, c->stream, false);
         if (st) return st;
@@ -1114,58 +1152,71 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         *ms = f;
         return VADX_OK;
     };
-    // the key needs the block length of this batch: plan once
+    // the key needs the block length of this batch: plan once (without slack)
     c->class_lanes = lanes;
+    c->slack = 0;
     c->planned = false;
     result = vadx_plan(c, &t, &need);
     if (result) { restore(); return result; }
     const std::string key = tune_key(c);
     std::map<int, int> cl;
     int ci = 0, cw = 0;
-    if (tune_lookup(cache_path, key, &cl, &ci, &cw)) {
+    int cs = 0;
+    if (tune_lookup(cache_path, key, &cl, &ci, &cw, &cs)) {
         for (auto &e : lanes)
             if (cl.count(e.first)) e.second = cl[e.first];
         best_l = lanes;
         best_i = ci;
         best_w = cw;
+        best_s = cs;
     } else {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             restore();
             return fail(c, VADX_E_HIP, "event creation failed");
         }
         double ms = 0.0;
-        result = trial(lanes, 1000, 2, &ms);    // warm-up (code load, caches)
-        if (result == VADX_OK) result = trial(lanes, 1000, 2, &ms);
+        result = trial(lanes, 1000, 2, 0, &ms);    // warm-up (code load, caches)
+        if (result == VADX_OK) result = trial(lanes, 1000, 2, 0, &ms);
         if (result == VADX_OK) best_ms = ms;
-        // each region-count class's lane budget in turn (the others at their
-        // best so far): floor(budget / n) instances per workgroup, one
-        // candidate per distinct instance count
-        for (auto &e : lanes) {
-            const int n = e.first;
-            for (int l = std::max(64, (n + 63) / 64 * 64); l <= 512 && result == VADX_OK; l += 64) {
-                if (l + 64 <= 512 && std::max(1, l / n) == std::max(1, (l + 64) / n)) continue;
-                if (l == best_l[n]) continue;
-                std::map<int, int> cand = best_l;
-                cand[n] = l;
-                result = trial(cand, 1000, 2, &ms);
-                if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_l = cand; }
+        // with and without wave slack, each region-count class's lane budget
+        // in turn (the others at their best so far for that slack):
+        // floor(budget / n) instances per workgroup, one candidate per
+        // distinct instance count
+        for (int sl : {0, 1}) {
+            std::map<int, int> sl_l = lanes;
+            double sl_ms = -1.0;
+            if (sl == 1 && result == VADX_OK) result = trial(sl_l, 1000, 2, 1, &sl_ms);
+            if (sl == 0) sl_ms = best_ms;
+            for (auto &e : lanes) {
+                const int n = e.first;
+                for (int l = std::max(64, (n + 63) / 64 * 64); l <= 512 && result == VADX_OK; l += 64) {
+                    if (l + 64 <= 512 && std::max(1, l / n) == std::max(1, (l + 64) / n)) continue;
+                    if (l == sl_l[n]) continue;
+                    std::map<int, int> cand = sl_l;
+                    cand[n] = l;
+                    result = trial(cand, 1000, 2, sl, &ms);
+                    if (result == VADX_OK && ms < sl_ms) { sl_ms = ms; sl_l = cand; }
+                }
             }
+            if (result == VADX_OK && sl_ms < best_ms) { best_ms = sl_ms; best_l = sl_l; best_s = sl; }
         }
-        // the register budget and the item length together, at the chosen lane budgets
+        // the register budget and the item length together, at the chosen lane
+        // budgets and slack
         for (int w : {2, 3})
             for (int it : {500, 1000, 2000, 3000, 4000, 8000}) {
                 if (result) break;
                 if (w == 2 && it == 1000) continue;
-                result = trial(best_l, it, w, &ms);
+                result = trial(best_l, it, w, best_s, &ms);
                 if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; best_w = w; }
             }
-        if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_w, best_ms);
+        if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_w, best_s, best_ms);
     }
     restore();
     if (result) return result;
     c->class_lanes = best_l;
     c->item_steps = best_i;
     c->occ = best_w;
+    c->slack = best_s;
     int widest = 64;
     for (auto &e : best_l) widest = std::max(widest, e.second);
     if (waves_out) *waves_out = best_w;

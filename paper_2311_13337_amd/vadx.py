@@ -28,7 +28,7 @@ EXPORTS = ("vadx_create", "vadx_destroy", "vadx_last_error", "vadx_model_default
            "vadx_plan", "vadx_integrate", "vadx_sync", "vadx_read_stats", "vadx_read_fc",
            "vadx_read_samples", "vadx_read_state", "vadx_read_trace", "vadx_instance_shape",
            "vadx_enable_timing", "vadx_kernel_time", "vadx_region_step_ops",
-           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_set_waves_per_simd", "vadx_launch_info", "vadx_class_lanes", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
+           "vadx_set_launch", "vadx_set_noise_keys", "vadx_set_graph", "vadx_autotune", "vadx_set_waves_per_simd", "vadx_launch_info", "vadx_class_lanes", "vadx_wave_slack", "vadx_mlp_create", "vadx_mlp_destroy", "vadx_mlp_last_error",
            "vadx_mlp_fit_target_norm", "vadx_mlp_get_target_norm", "vadx_mlp_set_target_norm",
            "vadx_mlp_get_params", "vadx_mlp_set_params", "vadx_mlp_grad", "vadx_mlp_train",
            "vadx_mlp_predict", "vadx_mlp_select", "vadx_analysis_defaults",
@@ -126,6 +126,7 @@ def lib():
             "vadx_set_waves_per_simd": (st, [vp, C.c_int32]),
             "vadx_launch_info": (st, [vp, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
             "vadx_class_lanes": (st, [vp, C.c_int32, C.c_int32, P(C.c_int32)]),
+            "vadx_wave_slack": (st, [vp, C.c_int32, P(C.c_int32)]),
             "vadx_plan": (st, [vp, P(vadx_run), P(C.c_size_t)]),
             "vadx_integrate": (st, [vp, P(vadx_run), vp, C.c_size_t]),
             "vadx_sync": (st, [vp]),
@@ -268,6 +269,12 @@ class Context:
 
     def vadx_set_waves_per_simd(self, waves: int):
         self._check(lib().vadx_set_waves_per_simd(self.h, waves))
+
+    def vadx_wave_slack(self, slack: int = -1) -> int:
+        """Sets the wave slack (0 or 1; -1 leaves it) and returns the setting."""
+        cur = C.c_int32(0)
+        self._check(lib().vadx_wave_slack(self.h, slack, C.byref(cur)))
+        return cur.value
 
     def vadx_set_graph(self, on: bool):
         self._check(lib().vadx_set_graph(self.h, 1 if on else 0))
@@ -501,8 +508,15 @@ class Sweep:
         return nbytes
 
     def autotune(self, cache_path=None, trial_steps=0):
-        """Tunes the launch shape for the planned run, then re-plans."""
-        choice = self.ctx.vadx_autotune(self.run, self.ws_ptr(), self.nbytes, cache_path,
+        """Tunes the launch shape for the planned run, then re-plans. The
+        workspace is first grown to what the run needs with wave slack (its
+        rings can be deeper), so that the trials can include it."""
+        slack = self.ctx.vadx_wave_slack()
+        self.ctx.vadx_wave_slack(1)
+        self.plan(self.run)
+        self.ctx.vadx_wave_slack(slack)
+        self.plan(self.run)
+        choice = self.ctx.vadx_autotune(self.run, self.ws_ptr(), self.ws.numel() - 256, cache_path,
                                         trial_steps)
         self.plan(self.run)
         return choice

@@ -437,10 +437,11 @@ def test_launch_shapes_are_bit_identical():
 
 
 def test_block_length_classes_are_bit_identical():
-    """Each instance steps in blocks of up to d_min + 1 steps of its own (8, 16,
-    24 or 32 here, one launch per block length); the coupling values do not depend
-    on the block length, so an instance run alone -- its own block class --
-    matches the same instance in the mixed batch bit for bit."""
+    """Each instance steps in blocks of up to d_min + 1 steps of its own (8, 12,
+    16, 24 or 32 here, all block lengths in one persistent launch); the coupling
+    values do not depend on the block length, so an instance run alone -- its
+    own block class -- matches the same instance in the mixed batch bit for
+    bit."""
     conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
     b = inputs.grid_uneven(18, seed=12)
     cfg = inputs.RunConfig(n_steps=640, transient_steps=160, seed=3)
@@ -460,6 +461,40 @@ def test_block_length_classes_are_bit_identical():
         one.sync()
         assert np.array_equal(one.ctx.vadx_read_state(0), sw.ctx.vadx_read_state(i)), i
         assert np.array_equal(one.ctx.vadx_read_fc(0), sw.ctx.vadx_read_fc(i)), i
+
+
+@pytest.mark.parametrize("lanes,mode", [(256, 0), (512, 0), (256, 1)])
+def test_wave_slack_is_bit_identical(lanes, mode):
+    """Wave slack halves the blocks of the slow-conduction instances (one block
+    more lag between the waves of an instance, a deeper ring) and leaves the
+    others alone; the sums and their order are the same, so every state, FC
+    matrix and sample matches the run without slack bit for bit, with one or
+    several instances per workgroup and in either launch mode."""
+    conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
+    b = inputs.grid_uneven(40, seed=21)
+    b.v[:] = np.maximum(b.v, 2.0)     # shortest delays of 50..54 steps at most
+    cfg = inputs.RunConfig(n_steps=1500, transient_steps=300, seed=5)
+    outs, blocks = [], []
+    for slack in (0, 1):
+        sw = vadx.Sweep(0, gpu_model("literature-B"))
+        ids = [sw.add_connectome(c) for c in conns]
+        sw.set_batch(b, conn_ids=ids)
+        for c in conns:
+            sw.ctx.vadx_class_lanes(c.n, lanes)
+        assert sw.ctx.vadx_wave_slack(slack) == slack
+        sw.ctx.vadx_set_launch(mode, 0, 480)
+        sw.plan(vadx.make_run(cfg))
+        sw.integrate()
+        sw.sync()
+        blocks.append(sw.ctx.vadx_launch_info()["steps_per_block"])
+        outs.append([(sw.ctx.vadx_read_state(i), sw.ctx.vadx_read_fc(i), sw.ctx.vadx_read_samples(i))
+                     for i in range(len(b))])
+    # the slowest instances (v = 2 m/s) have 32-step blocks without slack and
+    # 24-step ones with it; the fast ones (halved blocks under 12 steps) keep theirs
+    assert blocks == [32, 24], blocks
+    for i, (p0, p1) in enumerate(zip(*outs)):
+        for x0, x1 in zip(p0, p1):
+            assert np.array_equal(x0, x1), i
 
 
 def test_chunked_launches_are_bit_identical():
