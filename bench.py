@@ -46,7 +46,7 @@ def parse():
                    help="queue item length with --no-autotune (0 = 1000)")
     p.add_argument("--wave-slack", type=int, default=0, choices=[0, 1],
                    help="wave slack of the integration when not autotuning")
-    p.add_argument("--tune-steps", type=int, default=16000,
+    p.add_argument("--tune-steps", type=int, default=24000,
                    help="steps of each autotuner trial run")
     p.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "vadx_tune.json"))
     p.add_argument("--no-cpu-baseline", action="store_true")

@@ -269,7 +269,8 @@ vadx_status vadx_wave_slack(vadx_ctx *ctx, int32_t slack, int32_t *current);
  * trial_steps steps (0 = 2000; no samples) of `run` in `ws` (device, at least
  * the size vadx_plan gave for `run`; its contents are overwritten) of the
  * persistent launch. Starting from 256-lane budgets with 2 waves per SIMD
- * and 1000-step items, for wave slack 0 and 1 it tries each region-count
+ * and items of an eighth of the trial run (500..3000 steps), for wave slack 0
+ * and 1 it tries each region-count
  * class's lane budgets in turn (64..512 lanes, one per distinct instance count
  * per workgroup; the other classes at their best so far), keeps the faster
  * slack, then tries 2 or 3 waves per SIMD with items of 500..8000 steps at

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <limits>
@@ -1112,7 +1113,10 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
     for (int32_t ci : c->conn_of) lanes[c->conns[ci].n] = 256;
     vadx_status result = VADX_OK;
     std::map<int, int> best_l = lanes;
-    int best_i = 1000, best_w = 2, best_s = 0;
+    // lane budgets and slack are compared at items of an eighth of the trial
+    // run (500..3000 steps), so that each group still runs several items
+    const int i0 = (int)std::min<int64_t>(3000, std::max<int64_t>(500, t.n_steps / 8));
+    int best_i = i0, best_w = 2, best_s = 0;
     double best_ms = -1.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto restore = [&]() {
@@ -1127,6 +1131,8 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
+    // VADX_TUNE_LOG set: each trial's shape and time go to stderr
+    const bool tune_log = std::getenv("VADX_TUNE_LOG") != nullptr;
     auto trial = [&](const std::map<int, int> &l, int items, int occ, int slack, double *ms) -> vadx_status {
         c->class_lanes = l;
         c->item_steps = items;
@@ -1150,6 +1156,9 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         float f = 0.f;
         HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
         *ms = f;
+        if (tune_log)
+            std::fprintf(stderr, "[vadx autotune] lanes %s slack %d waves %d items %d: %.3f ms\n",
+                         lanes_str(l).c_str(), slack, occ, items, f);
         return VADX_OK;
     };
     // the key needs the block length of this batch: plan once (without slack)
@@ -1175,8 +1184,8 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
             return fail(c, VADX_E_HIP, "event creation failed");
         }
         double ms = 0.0;
-        result = trial(lanes, 1000, 2, 0, &ms);    // warm-up (code load, caches)
-        if (result == VADX_OK) result = trial(lanes, 1000, 2, 0, &ms);
+        result = trial(lanes, i0, 2, 0, &ms);    // warm-up (code load, caches)
+        if (result == VADX_OK) result = trial(lanes, i0, 2, 0, &ms);
         if (result == VADX_OK) best_ms = ms;
         // with and without wave slack, each region-count class's lane budget
         // in turn (the others at their best so far for that slack):
@@ -1185,7 +1194,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         for (int sl : {0, 1}) {
             std::map<int, int> sl_l = lanes;
             double sl_ms = -1.0;
-            if (sl == 1 && result == VADX_OK) result = trial(sl_l, 1000, 2, 1, &sl_ms);
+            if (sl == 1 && result == VADX_OK) result = trial(sl_l, i0, 2, 1, &sl_ms);
             if (sl == 0) sl_ms = best_ms;
             for (auto &e : lanes) {
                 const int n = e.first;
@@ -1194,7 +1203,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
                     if (l == sl_l[n]) continue;
                     std::map<int, int> cand = sl_l;
                     cand[n] = l;
-                    result = trial(cand, 1000, 2, sl, &ms);
+                    result = trial(cand, i0, 2, sl, &ms);
                     if (result == VADX_OK && ms < sl_ms) { sl_ms = ms; sl_l = cand; }
                 }
             }
@@ -1205,7 +1214,7 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
         for (int w : {2, 3})
             for (int it : {500, 1000, 2000, 3000, 4000, 8000}) {
                 if (result) break;
-                if (w == 2 && it == 1000) continue;
+                if (w == 2 && it == i0) continue;
                 result = trial(best_l, it, w, best_s, &ms);
                 if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; best_w = w; }
             }

@@ -563,10 +563,10 @@ def test_graph_replay_matches_eager():
 
 
 def test_autotuner_choice_cached_and_result_unchanged(tmp_path):
-    """The autotuner picks a lane budget per region count, a register budget
-    and a queue item length for a mixed batch, stores them in the JSON cache,
-    reads them back without trials, and the tuned shape gives the same bits as
-    the default one."""
+    """The autotuner picks a lane budget per region count, the wave slack, a
+    register budget and a queue item length for a mixed batch, stores them in
+    the JSON cache, reads them back without trials, and the tuned shape gives
+    the same bits as the default one."""
     import json
     conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
     b = inputs.grid_uneven(60, seed=11)
@@ -587,7 +587,10 @@ def test_autotuner_choice_cached_and_result_unchanged(tmp_path):
     assert sorted(per_class) == [68, 84, 200] and max(per_class.values()) == lanes
     assert all(sw.ctx.vadx_class_lanes(n) == l for n, l in per_class.items())
     assert entry["waves_per_simd"] == waves and entry["item_steps"] == items
+    assert entry["wave_slack"] in (0, 1) and sw.ctx.vadx_wave_slack() == entry["wave_slack"]
+    sw.ctx.vadx_wave_slack(1 - entry["wave_slack"])
     assert sw.autotune(cache, trial_steps=200) == (lanes, items, waves)
+    assert sw.ctx.vadx_wave_slack() == entry["wave_slack"]
     sw.integrate()
     sw.sync()
     for i in range(len(b)):
