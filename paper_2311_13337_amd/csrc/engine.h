@@ -13,9 +13,9 @@ namespace vadx {
 // before writing any of its own rates, which is exact as long as
 // B <= d_min + 1 (the shortest delay plus one).
 constexpr int kMaxBlock = 32;
-// With wave slack a block is at most (d_min + 1) / 2 steps, so it reads only
-// rates published two blocks back and the waves of an instance may drift a
-// block further apart; taken only where such a block is still this long.
+// With wave slack a block is at most (d_min + 1) / 2 steps, so the waves of an
+// instance may drift at least a block apart; taken only where such a block is
+// still this long.
 constexpr int kSlackMinBlock = 12;
 
 // One instance = one parameter combination on one connectome.
@@ -52,8 +52,8 @@ struct GroupDev {
     int32_t first;      // into the instance permutation
     int32_t count;
     int32_t n;
-    int32_t block;      // steps per block (<= d_min + 1 of every instance; <= (d_min + 1) / 2 with lag 1)
-    int32_t lag;        // blocks a wave may run ahead of the waves it shares instances with, minus one (0 or 1)
+    int32_t block;      // steps per block (<= d_min + 1 of every instance)
+    int32_t dmin;       // shortest delay in steps over the group's instances
 };
 
 struct DelayTableDev {

@@ -123,7 +123,7 @@ template <int B> constexpr int kGatherEdges =
     B >= kGatherFloats<B> ? 1 : (kGatherFloats<B> / B > 8 ? 8 : kGatherFloats<B> / B);
 
 // Waits until every wave in [lo, hi] other than `self` has published m
-// blocks of the current item (per-wave counters in LDS), then acquires their
+// steps of the current item (per-wave counters in LDS), then acquires their
 // history writes. The wait is bounded: on timeout bit 1 of *status is set
 // and the wave goes on (its results are then void, and the run reports it),
 // so no wave can wait forever. Every argument is wave-uniform.
@@ -148,13 +148,14 @@ __device__ __forceinline__ void wait_waves(const int *wdone, int lo, int hi, int
 // Integrates the instances of group g over steps [n_begin, n_end). All
 // threads of the workgroup call it with the same (wave-uniform) arguments: it
 // starts with a workgroup barrier. Inside, waves synchronise only with the
-// waves that share an instance with them: before the gather of block m a
-// wave waits until those waves have written the histories of block m-1
-// (m-2 for groups with lag 1, whose blocks are at most (d_min + 1) / 2 steps)
-// (counters in LDS, `wdone`), so waves of different instances drift apart
-// by up to 1 + lag blocks instead of meeting at a barrier after every block.
-// The ring depth (d_max + (1 + lag) B + 1) keeps a block's writes clear of
-// every slot a wave that far behind still reads.
+// waves that share an instance with them: each wave publishes the number of
+// steps whose rates it has written (counters in LDS, `wdone`), and before the
+// gather of the block from step s it waits until those waves have written
+// slot s + B - 1 - d_min (the newest its reads reach, d_min the group's
+// shortest delay). Waves thus drift up to d_min + 1 - B steps apart instead of
+// meeting at a barrier after every block; the ring depth (d_max + d_min + 2)
+// keeps a wave's writes clear of every slot a wave that far behind still
+// reads.
 //
 template <int B, int VAR>
 __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const GroupDev g,
@@ -235,11 +236,12 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
     float *myrow = active ? ring + (int64_t)k * Dp : nullptr;
     float z4[4] = {0.f, 0.f, 0.f, 0.f};
 
-    int m = 0;   // blocks published by this wave
-    for (int64_t n0 = n_begin; n0 < n_end && wave_live; n0 += B, ++m) {
+    for (int64_t n0 = n_begin; n0 < n_end && wave_live; n0 += B) {
         const int nb = (int)((n_end - n0) < B ? (n_end - n0) : B);
-        // block m reads rates published by the end of block m - 1 - lag
-        if (m > g.lag) wait_waves(wdone, wlo, whi, wave, m - g.lag, a.status, a.wait_spins);
+        // steps of this item the other waves must have published: the block
+        // reads slots up to n0 + B - 1 - d_min (earlier items' slots are all written)
+        const int need = (int)(n0 - n_begin) + B - 1 - g.dmin;
+        if (need > 0) wait_waves(wdone, wlo, whi, wave, need, a.status, a.wait_spins);
         if (active) {
             // coupling of steps n0 .. n0+nb-1: S sum_j W_kj H_j[n - d_kj], in the
             // fixed (ascending j) order of the CSR row
@@ -253,7 +255,7 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
                 // they are, so a round costs one memory round trip. Past the
                 // row's end a round re-reads the row's last edge with weight 0.
                 // The sums run over the edges in row order. Offsets stay in 32
-                // bits: j < 512 regions and ring rows under 2^20 + 64 slots, so
+                // bits: j < 512 regions and ring rows under 2^21 + 32 slots, so
                 // j * Dp fits the 24-bit multiplier and the offset an int.
                 constexpr int U = kGatherEdges<B>;
                 // the row bounds pass through an empty asm so that the first
@@ -379,7 +381,8 @@ __device__ __forceinline__ void integrate_group(const IntegrateArgs &a, const Gr
         // publish this block's history to the waves that share its instances
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if ((tid & 63) == 0)
-            __hip_atomic_store(&wdone[wave], m + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&wdone[wave], (int)(n0 + nb - n_begin), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     if (active) {
         double *st = reinterpret_cast<double *>(a.ws + I.state_off);

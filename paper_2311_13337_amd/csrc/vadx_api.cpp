@@ -144,7 +144,7 @@ struct vadx_ctx {
     int wg_lanes = 256;                  // lane budget per workgroup (autotuned)
     std::map<int, int> class_lanes;      // lane budget per region count (autotuned; else wg_lanes)
     int occ = 2;                         // waves per SIMD of the persistent kernel (autotuned)
-    int slack = 0;                       // half-length blocks with one block of lag where they stay long (autotuned)
+    int slack = 0;                       // half-length blocks where they stay long (autotuned)
     int item_steps = 1000;
     int cus = 0;
 };
@@ -455,22 +455,24 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     const int64_t ni = (int64_t)c->S.size();
     if (ni == 0) return fail(c, VADX_E_STATE, "no batch set");
     const int64_t ns = (r->n_steps - r->transient_steps) / r->tavg_steps;
-    // ring depths and block lengths: a block of B steps reads histories up to
-    // B-1 steps ahead of its first step, so B <= d_min + 1 (each instance's own
-    // shortest delay) lets it read what the waves of its instance published
-    // by the end of the previous block. With lag 1 (wave slack, where the half
-    // length is still >= kSlackMinBlock steps) B <= (d_min + 1) / 2, so a block
-    // reads only what was published two blocks back and a wave may run a block
-    // further ahead of the others. Rings hold d_max + (1 + lag) B + 1 slots: the
-    // furthest a wave can write ahead of the oldest slot another wave of its
-    // instance still has to read.
-    std::vector<int64_t> dmax(ni);
-    std::vector<int> blk(ni), lag(ni);
+    // ring depths and block lengths: a block of B steps from step s reads
+    // histories up to slot s + B - 1 - d_min, so B <= d_min + 1 (each
+    // instance's own shortest delay) keeps every read at or before the block's
+    // first slot. The waves of a group wait before a block only until the
+    // others have written that slot (d_min of the group), so they may drift up
+    // to d_min + 1 - B steps apart; with wave slack B <= (d_min + 1) / 2 where
+    // that is still >= kSlackMinBlock steps. A wave then writes at most
+    // d_min + 1 slots ahead of the next block start of any other wave of its
+    // instance, which reads back to d_max slots before that: rings hold
+    // d_max + d_min + 2 slots.
+    std::vector<int64_t> dmax(ni), dmin(ni);
+    std::vector<int> blk(ni);
     int bmax = 1;
     for (int64_t i = 0; i < ni; ++i) {
         const HostConn &hc = c->conns[c->conn_of[i]];
         const int64_t dm = hc.nnz ? host_delay(hc.len_min, c->v[i], r->dt_ms) : 1;
         dmax[i] = hc.nnz ? host_delay(hc.len_max, c->v[i], r->dt_ms) : 1;
+        dmin[i] = std::min(dm, dmax[i]);
         if (dmax[i] >= (1 << 20) - 2 * kMaxBlock - 2)
             return fail(c, VADX_E_UNSUPPORTED, "delay of %lld steps too long", (long long)dmax[i]);
         // the longest of 1, 2, 4, 8, 12, 16, 24, 32 steps within the bound
@@ -479,8 +481,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
             if (cand <= kMaxBlock && cand <= dm + 1) B = cand;
             if (cand <= kMaxBlock && 2 * cand <= dm + 1) Bh = cand;
         }
-        lag[i] = (c->slack && Bh >= kSlackMinBlock) ? 1 : 0;
-        blk[i] = lag[i] ? Bh : B;
+        blk[i] = (c->slack && Bh >= kSlackMinBlock) ? Bh : B;
         bmax = std::max(bmax, blk[i]);
     }
     c->block = bmax;
@@ -516,8 +517,8 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     for (int64_t i = 0; i < ni; ++i) order[i] = (int32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         if (blk[a] != blk[b]) return blk[a] > blk[b];
-        if (lag[a] != lag[b]) return lag[a] < lag[b];
         if (c->conn_of[a] != c->conn_of[b]) return c->conn_of[a] < c->conn_of[b];
+        if (dmin[a] != dmin[b]) return dmin[a] < dmin[b];
         return dmax[a] < dmax[b];
     });
     c->h_groups.clear();
@@ -525,19 +526,21 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
     c->classes.clear();
     for (int64_t s = 0; s < ni;) {
         const int32_t cid = c->conn_of[order[s]];
-        const int B = blk[order[s]], L = lag[order[s]];
+        const int B = blk[order[s]];
         const int n = c->conns[cid].n;
         const auto cl = c->class_lanes.find(n);
         int per = std::max(1, (cl != c->class_lanes.end() ? cl->second : c->wg_lanes) / n);
         if (c->wg_instances_override > 0) per = std::min(per, c->wg_instances_override);
         int64_t e = s;
-        while (e < ni && e - s < per && c->conn_of[order[e]] == cid && blk[order[e]] == B &&
-               lag[order[e]] == L)
+        int64_t gmin = dmin[order[s]];
+        while (e < ni && e - s < per && c->conn_of[order[e]] == cid && blk[order[e]] == B) {
+            gmin = std::min(gmin, dmin[order[e]]);
             ++e;
+        }
         if (c->classes.empty() || c->classes.back().block != B)
             c->classes.push_back(BlockClass{B, (int32_t)c->h_groups.size(), 0, 64});
         BlockClass &bc = c->classes.back();
-        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, B, L});
+        c->h_groups.push_back(GroupDev{(int32_t)s, (int32_t)(e - s), n, B, (int32_t)gmin});
         bc.n_groups += 1;
         bc.threads = std::max(bc.threads, (int)(((e - s) * n + 63) / 64 * 64));
         s = e;
@@ -561,7 +564,7 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         d.cF[2] = (float)ip(VADX_P_CF_IE, c->model.cF_ie);
         d.cF[3] = (float)ip(VADX_P_CF_II, c->model.cF_ii);
         d.n = hc.n;
-        d.D = (int32_t)(dmax[i] + (1 + lag[i]) * blk[i] + 1);
+        d.D = (int32_t)(dmax[i] + dmin[i] + 2);
         d.Dp = d.D + blk[i] - 1;
         d.conn = c->conn_of[i];
         d.id = c->noise_key[(size_t)i];
