@@ -273,8 +273,10 @@ vadx_status vadx_wave_slack(vadx_ctx *ctx, int32_t slack, int32_t *current);
  * and 1 it tries each region-count
  * class's lane budgets in turn (64..512 lanes, one per distinct instance count
  * per workgroup; the other classes at their best so far), keeps the faster
- * slack, then tries 2 or 3 waves per SIMD with items of 500..8000 steps at
- * the chosen budgets, and keeps the fastest. With a cache_path (nullable) the
+ * slack, tries 3 waves per SIMD at the chosen budgets, then items of
+ * 500..8000 steps over trial runs as long as `run` (at most
+ * max(trial_steps, 60000) steps, so that the queue's tail weighs as in the
+ * run), and keeps the fastest. With a cache_path (nullable) the
  * choice is read from / added to that JSON file, keyed by device, longest
  * block length (without slack) and the region-count mix; a cached choice is
  * applied without trials. *lanes (the widest class budget), *item_steps,

@@ -1212,15 +1212,23 @@ extern "C" vadx_status vadx_autotune(vadx_ctx *c, const vadx_run *r, void *ws, s
             }
             if (result == VADX_OK && sl_ms < best_ms) { best_ms = sl_ms; best_l = sl_l; best_s = sl; }
         }
-        // the register budget and the item length together, at the chosen lane
-        // budgets and slack
-        for (int w : {2, 3})
-            for (int it : {500, 1000, 2000, 3000, 4000, 8000}) {
-                if (result) break;
-                if (w == 2 && it == i0) continue;
-                result = trial(best_l, it, w, best_s, &ms);
-                if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; best_w = w; }
-            }
+        // the register budget at the chosen lane budgets and slack
+        if (result == VADX_OK) {
+            result = trial(best_l, i0, 3, best_s, &ms);
+            if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_w = 3; }
+        }
+        // the item length, over trial runs as long as the run itself (at most
+        // max(trial_steps, 60000) steps): the queue's tail is a share of the
+        // run that grows with the item length, so short trials would favour
+        // short items
+        t.n_steps = std::min<int64_t>(r->n_steps, std::max<int64_t>(t.n_steps, 60000));
+        t.transient_steps = t.n_steps;
+        best_ms = std::numeric_limits<double>::infinity();
+        for (int it : {500, 1000, 2000, 3000, 4000, 8000}) {
+            if (result) break;
+            result = trial(best_l, it, best_w, best_s, &ms);
+            if (result == VADX_OK && ms < best_ms) { best_ms = ms; best_i = it; }
+        }
         if (result == VADX_OK) tune_store(cache_path, key, best_l, best_i, best_w, best_s, best_ms);
     }
     restore();
