@@ -204,12 +204,16 @@ def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
     launch_ms = ms_int / n_int
     achieved = flop_rs * rs_per_launch / (launch_ms / 1000.0) / 1e12
     # HBM bytes of the integration kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
-    # (copy-calibrated), stored per region-step for this kernel source
+    # (copy-calibrated), stored per region-step for this kernel source and
+    # launch shape (the block length and the workgroup's lanes change them)
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        if tj.get("workload") == workload_name and tj.get("kernel_source_sha") == _src_sha():
+        here = {"class_lanes": {str(k): v for k, v in shape["class_lanes"].items()},
+                "wave_slack": shape.get("wave_slack"), "steps_per_block": shape.get("steps_per_block")}
+        same_shape = tj.get("shape") == here
+        if tj.get("workload") == workload_name and tj.get("kernel_source_sha") == _src_sha() and same_shape:
             traffic = round(tj["bytes_per_region_step"] * rs_per_launch)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
