@@ -245,8 +245,8 @@ def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the sweep on a single MI355X "
-              "(instances shard across GPUs without communication; see the design notes). "
+        print("bench.py measures one GPU only: the engine runs a sweep on a single MI355X "
+              "(instances would shard across GPUs without communication). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
