@@ -52,8 +52,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-instances", type=int, default=64)
     p.add_argument("--cpu-sample-steps", type=int, default=10000)
-    p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_uniform.json"),
-                   help="HBM bytes per launch measured with rocprofv3 counters, if present")
+    p.add_argument("--traffic-json", default="",
+                   help="HBM bytes per region-step measured with rocprofv3 counters (default: "
+                        "profiles/traffic_<workload>.json, if present)")
     p.add_argument("--no-analysis", action="store_true",
                    help="skip the analysis-metric pass over the sweep's samples")
     p.add_argument("--analysis-reps", type=int, default=3)
@@ -207,11 +208,11 @@ def measure(args, conns, batch, cfg, desc, workload_name, steps, warmup):
     # (copy-calibrated), stored per region-step for this kernel source and
     # launch shape (the block length and the workgroup's lanes change them)
     traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
+    traffic_json = args.traffic_json or os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
+    if os.path.exists(traffic_json):
+        with open(traffic_json) as f:
             tj = json.load(f)
-        here = {"class_lanes": {str(k): v for k, v in shape["class_lanes"].items()},
-                "wave_slack": shape.get("wave_slack"), "steps_per_block": shape.get("steps_per_block")}
+        here = {k: shape.get(k) for k in ("groups", "block_threads", "steps_per_block", "wave_slack")}
         same_shape = tj.get("shape") == here
         if tj.get("workload") == workload_name and tj.get("kernel_source_sha") == _src_sha() and same_shape:
             traffic = round(tj["bytes_per_region_step"] * rs_per_launch)
