@@ -545,6 +545,20 @@ vadx_status vadx_plan(vadx_ctx *c, const vadx_run *r, size_t *bytes)
         bc.threads = std::max(bc.threads, (int)(((e - s) * n + 63) / 64 * 64));
         s = e;
     }
+    // within each block length, the groups of different connectomes take
+    // turns in the queue, so that the workgroups sharing a CU tend to hold
+    // rows of different lengths and their gathers' memory waits overlap less
+    // (uneven batch: 1 % faster; results do not depend on the order)
+    for (BlockClass &bc : c->classes) {
+        std::vector<GroupDev> g(c->h_groups.begin() + bc.first, c->h_groups.begin() + bc.first + bc.n_groups);
+        std::map<int, std::vector<GroupDev>> by_conn;
+        for (const GroupDev &x : g) by_conn[c->conn_of[c->h_perm[x.first]]].push_back(x);
+        std::vector<GroupDev> turns;
+        for (size_t r = 0; turns.size() < g.size(); ++r)
+            for (auto &kv : by_conn)
+                if (r < kv.second.size()) turns.push_back(kv.second[r]);
+        std::copy(turns.begin(), turns.end(), c->h_groups.begin() + bc.first);
+    }
     c->wg_threads = 64;
     for (const BlockClass &bc : c->classes) c->wg_threads = std::max(c->wg_threads, bc.threads);
     // workspace layout (floats unless noted), each section 256-byte aligned
