@@ -143,8 +143,28 @@ def fc_verdict(label, fc, st, ens, q):
     return True, ""
 
 
-def check_fc(label, fc, st, ens, q):
-    """fc: GPU FC [n, n]; st: GPU vadx_stats row; ens: oracle ensemble outputs."""
+def within_path_distribution(st, paths):
+    """Whether every statistic of one GPU run lies within the range of the
+    oracle's runs of the same instance over other noise paths (paths: [P, 6]),
+    widened by the statistics' tolerances."""
+    gst = np.array([st[k] for k in vadx.STAT_NAMES], np.float64)
+    lo, hi = paths.min(axis=0), paths.max(axis=0)
+    tol = np.array([TOL_FC, TOL_FC, TOL_FC, 0, 0, TOL_FC]) + np.array([0, 0, 0, 1, 1, 0]) * (
+        1e-2 * np.abs(paths.mean(axis=0)) + 1e-3)
+    return bool(np.all((gst >= lo - tol) & (gst <= hi + tol)))
+
+
+def check_fc(label, fc, st, ens, q, paths=None):
+    """fc: GPU FC [n, n]; st: GPU vadx_stats row; ens: oracle ensemble outputs
+    (the same noise path, initial rates perturbed). paths (optional): the
+    oracle's statistics of the same instance over other noise paths [P, 6]. A
+    chaotic run that fails the same-path criteria passes if its statistics lie
+    within the oracle's own distribution over those paths: a quiet state can
+    re-ignite under perturbations as small as single-precision rounding, in a
+    few per cent of the oracle's FP64 runs over noise paths (excursions that an
+    ensemble of initial perturbations on one noise path, which relax in the
+    quiet state, cannot show); test_fc_distribution_over_noise_paths holds the
+    GPU's distribution over those paths to the oracle's."""
     ref = ens[0]["fc"][q]
     spread = max(np.abs(e["fc"][q] - ref).max() for e in ens[1:])
     gst = np.array([st[k] for k in vadx.STAT_NAMES], np.float64)
@@ -154,6 +174,11 @@ def check_fc(label, fc, st, ens, q):
           f"{spread:.3g}; fc_mean gpu {gst[0]:.4f} oracle {ost[:, 0].min():.4f}.."
           f"{ost[:, 0].max():.4f}", flush=True)
     ok, msg = fc_verdict(label, fc, st, ens, q)
+    if not ok and paths is not None and spread >= 1e-3 and (st["flags"] & 1) == 0:
+        ok = within_path_distribution(st, paths)
+        print(f"[parity] {label}: same-path criteria not met ({msg}); within the oracle's "
+              f"distribution over {len(paths)} noise paths: {ok} (fc_mean {paths[:, 0].min():.4f}.."
+              f"{paths[:, 0].max():.4f})", flush=True)
     assert ok, msg
 
 
@@ -226,7 +251,65 @@ def test_first_1000_steps_small_grid(oracle, preset):
     print(f"[parity] {preset}: {full} of 8 instances predictable over the whole window", flush=True)
 
 
-def test_fc_and_stats_small_grid_full_run(oracle):
+N_PATHS = 96
+
+
+@pytest.fixture(scope="module")
+def small_grid_paths(oracle):
+    """Statistics of the small grid over N_PATHS noise paths (noise key
+    1000 p + i for path p of point i; path 0 is the default run): the FP64
+    oracle's and the GPU's, each [N_PATHS, 8, 6]."""
+    conn = inputs.synthetic_connectome(68)
+    base = inputs.grid_small()
+    nb = len(base)
+    idx = np.tile(np.arange(nb), N_PATHS)
+    keys = (np.repeat(np.arange(N_PATHS), nb) * 1000 + np.tile(np.arange(nb), N_PATHS)).astype(np.uint32)
+    batch = base.subset(idx.tolist())
+    print(f"[parity] small grid over {N_PATHS} noise paths: oracle and GPU", flush=True)
+    o = oracle.run(oracle_model(oracle, "literature-B"), inputs.RUN_SMALL, conn, batch, inst_ids=keys,
+                   n_threads=NTHREADS, want_samples=False)["stats"].reshape(N_PATHS, nb, 6)
+    sw = vadx.Sweep(0, gpu_model("literature-B"))
+    sw.add_connectome(conn)
+    sw.set_batch(batch, noise_keys=keys.tolist())
+    sw.plan(vadx.make_run(inputs.RUN_SMALL))
+    sw.integrate()
+    sw.sync()
+    st = sw.stats()
+    g = np.array([[row[k] for k in vadx.STAT_NAMES] for row in st], np.float64).reshape(N_PATHS, nb, 6)
+    assert np.all((st["flags"] & 1) == 0)
+    return o, g
+
+
+def test_fc_distribution_over_noise_paths(small_grid_paths):
+    """Distributional parity where single runs are not predictable: over 96
+    noise paths, each small-grid point's statistics on the GPU and in the FP64
+    oracle have the same means (within 0.01, or 1 % for the rates, plus four
+    standard errors of the difference), interquartile ranges within a factor
+    of two (a spread that the rare excursions do not dominate), and the same
+    frequency of excursions (fc_mean more than 0.1 below the oracle's median:
+    a quiet state re-igniting) within four standard deviations of the
+    counts."""
+    o, g = small_grid_paths
+    for i in range(o.shape[1]):
+        for j, name in enumerate(vadx.STAT_NAMES[:6]):
+            mo, mg = o[:, i, j].mean(), g[:, i, j].mean()
+            so, sg = o[:, i, j].std(ddof=1), g[:, i, j].std(ddof=1)
+            se = np.sqrt((so ** 2 + sg ** 2) / N_PATHS)
+            tol = (1e-2 * abs(mo) + 1e-4) if name in ("rate_mean_hz", "rate_std_hz") else 1e-2
+            assert abs(mg - mo) <= tol + 4 * se, (i, name, mg, mo, se)
+            qo = np.subtract(*np.percentile(o[:, i, j], [75, 25]))
+            qg = np.subtract(*np.percentile(g[:, i, j], [75, 25]))
+            if qo > 1e-3 * max(abs(mo), 1e-3):
+                assert 0.5 <= qg / qo <= 2.0, (i, name, qg, qo)
+        thr = np.median(o[:, i, 0]) - 0.1
+        no, ng = int((o[:, i, 0] < thr).sum()), int((g[:, i, 0] < thr).sum())
+        print(f"[parity] small grid point {i} over {N_PATHS} noise paths: fc_mean gpu "
+              f"{g[:, i, 0].mean():.4f} +- {g[:, i, 0].std():.4f}, oracle {o[:, i, 0].mean():.4f} +- "
+              f"{o[:, i, 0].std():.4f}; excursions gpu {ng}, oracle {no}", flush=True)
+        assert abs(ng - no) <= 4 * np.sqrt(ng + no) + 2, (i, ng, no)
+
+
+def test_fc_and_stats_small_grid_full_run(oracle, small_grid_paths):
     conn = inputs.synthetic_connectome(68)
     batch = inputs.grid_small()
     cfg = inputs.RUN_SMALL
@@ -235,8 +318,11 @@ def test_fc_and_stats_small_grid_full_run(oracle):
     check_fc_samples(oracle, sw, range(len(batch)), lambda i: conn, "small grid")
     ens = oracle_ensemble(oracle, "literature-B", conn, batch, cfg)
     st = sw.stats()
+    paths, gpaths = small_grid_paths
     for i in range(len(batch)):
-        check_fc(f"small grid instance {i}", sw.ctx.vadx_read_fc(i), st[i], ens, i)
+        # path 0 of the noise-path runs is this run
+        assert np.allclose(gpaths[0, i], [st[i][k] for k in vadx.STAT_NAMES], rtol=0, atol=0)
+        check_fc(f"small grid instance {i}", sw.ctx.vadx_read_fc(i), st[i], ens, i, paths=paths[:, i])
 
 
 def test_long_run_uniform_sweep_sampled(oracle):
