@@ -391,6 +391,58 @@ def test_long_run_uneven_batch_sampled(oracle):
                  sw.ctx.vadx_read_fc(i), st[i], ens, 0)
 
 
+def test_fc_distribution_over_noise_paths_by_region_count(oracle):
+    """The same distributional parity for one active instance of each region
+    count of the uneven batch (68 regions at 1.66 m/s, 84 at 5.75 m/s, 200 at
+    9.34 m/s; 32-, 16- and 8-step blocks), 48 noise paths of 2-s runs each, all
+    on the GPU in one mixed batch: per instance and statistic, the mean of the
+    paired differences (GPU minus oracle on the same noise path) within 0.01
+    (1 % for rates) plus four of its standard errors, and interquartile ranges
+    within a factor of 2.5."""
+    conns = [inputs.synthetic_connectome(n) for n in (68, 84, 200)]
+    full = inputs.grid_uneven(8192, seed=3)
+    pick = [324, 483, 4]
+    P = 48
+    cfg = inputs.RunConfig(n_steps=20000, transient_steps=5000)
+    idx = np.repeat(pick, P)
+    keys = (np.tile(np.arange(P), len(pick)) * 100000 + idx).astype(np.uint32)
+    batch = full.subset(idx.tolist())
+    print(f"[parity] {len(pick)} instances x {P} noise paths x 2 s, GPU (one mixed batch) and oracle", flush=True)
+    sw = vadx.Sweep(0, gpu_model("literature-B"))
+    ids = [sw.add_connectome(c) for c in conns]
+    sw.set_batch(batch, conn_ids=ids, noise_keys=keys.tolist())
+    sw.plan(vadx.make_run(cfg))
+    sw.integrate()
+    sw.sync()
+    st = sw.stats()
+    g = np.array([[row[k] for k in vadx.STAT_NAMES] for row in st], np.float64).reshape(len(pick), P, 6)
+    assert np.all((st["flags"] & 1) == 0)
+
+    def oracle_paths(q):
+        c = int(full.conn[pick[q]])
+        sub = full.subset([pick[q]] * P)
+        return run_oracle(oracle, "literature-B", conns[c], sub, cfg, inst_ids=keys[q * P:(q + 1) * P],
+                          want_samples=False)["stats"]
+
+    o = np.array([oracle_paths(q) for q in range(len(pick))])   # each over the host's threads
+    for q, i in enumerate(pick):
+        for j, name in enumerate(vadx.STAT_NAMES[:6]):
+            dlt = g[q, :, j] - o[q, :, j]
+            se = dlt.std(ddof=1) / np.sqrt(P)
+            mo = o[q, :, j].mean()
+            tol = (1e-2 * abs(mo) + 1e-4) if name in ("rate_mean_hz", "rate_std_hz") else 1e-2
+            assert abs(dlt.mean()) <= tol + 4 * se, (i, name, dlt.mean(), se)
+            qo = np.subtract(*np.percentile(o[q, :, j], [75, 25]))
+            qg = np.subtract(*np.percentile(g[q, :, j], [75, 25]))
+            if qo > 1e-3 * max(abs(mo), 1e-3):
+                assert 0.4 <= qg / qo <= 2.5, (i, name, qg, qo)
+        print(f"[parity] instance {i} ({conns[int(full.conn[i])].n} regions) over {P} noise paths: "
+              f"fc_mean gpu {g[q, :, 0].mean():.4f} +- {g[q, :, 0].std():.4f}, oracle "
+              f"{o[q, :, 0].mean():.4f} +- {o[q, :, 0].std():.4f}; paired difference "
+              f"{(g[q, :, 0] - o[q, :, 0]).mean():+.4f} +- {(g[q, :, 0] - o[q, :, 0]).std(ddof=1) / np.sqrt(P):.4f}",
+              flush=True)
+
+
 def test_ragged_groups_and_short_delays(oracle):
     """37 regions (not a multiple of 64), 11 instances over several workgroups,
     delays of 1-3 steps, so blocks between barriers are 2 steps long."""
