@@ -148,36 +148,63 @@ __device__ inline float wave_sum(float v)
 
 // ------------------------------------------------------------------ transpose
 // Window of instance i ([Na][n] at the tail of its [n_samples][n] block) to
-// rows xT[rbase + k][t]. Workgroup: 64 x 4 threads, one 64 x 64 tile.
-__global__ __launch_bounds__(256) void an_transpose_kernel(AnChunk a, int ktiles_max)
+// rows xT[rbase + k][t]. A workgroup (256 threads) moves 64 samples of up to
+// kTrRegions regions: with n <= kTrRegions that is one contiguous run of the
+// source, read in order (consecutive threads, consecutive floats); each wave
+// then writes 64-sample pieces (256 B) of its rows.
+constexpr int kTrRegions = 128;
+constexpr int kTrPerThread = 64 * kTrRegions / 256;   // tile elements per thread, at most
+
+__global__ __launch_bounds__(256) void an_transpose_kernel(AnChunk a, int kchunks_max)
 {
-    __shared__ float tile[64][65];
+    __shared__ float tile[64][kTrRegions + 1];    // odd row pitch: column reads hit distinct banks
     const int i = blockIdx.y;
     const int n = a.n[i];
-    const int kt = blockIdx.x % ktiles_max, tt = blockIdx.x / ktiles_max;
-    if (kt * 64 >= n) return;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const float *src = a.samples + a.samp_off[i] + (a.n_samples - a.Na) * (int64_t)n;
-    const int k = kt * 64 + tx;
-    for (int r = ty; r < 64; r += 4) {
-        const int t = tt * 64 + r;
-        tile[r][tx] = (k < n && t < a.Na) ? src[(int64_t)t * n + k] : 0.f;
+    const int kc = blockIdx.x % kchunks_max, tt = blockIdx.x / kchunks_max;
+    const int k0 = kc * kTrRegions;
+    if (k0 >= n) return;
+    const int kw = min(kTrRegions, n - k0);
+    const int t0 = tt * 64;
+    const int rows = min(64, a.Na - t0);
+    const float *src = a.samples + a.samp_off[i] + (a.n_samples - a.Na + t0) * (int64_t)n + k0;
+    // thread tid takes tile elements e = tid + 256 j, row r = floor(e / kw),
+    // column e - r kw: source offset e + r (n - kw), LDS offset e + r (pitch -
+    // kw). All its loads are issued before the first is stored to LDS. r is
+    // taken as (e + 1/2) times the rounded reciprocal of kw, truncated: for
+    // e < 2^13 and kw <= 128 the quotient stays at least 1/256 from an integer
+    // and its rounding error is below 1e-5, so r is exact.
+    const float inv_kw = 1.f / (float)kw;
+    const int ne = rows * kw;
+    const uint32_t src_gap = (uint32_t)(n - kw), lds_gap = (uint32_t)(kTrRegions + 1 - kw);
+    const float eh = (float)threadIdx.x + 0.5f;
+    float v[kTrPerThread];
+    uint32_t lo[kTrPerThread];
+#pragma unroll
+    for (int j = 0; j < kTrPerThread; ++j) {
+        const uint32_t e = threadIdx.x + 256u * j;
+        const uint32_t r = (uint32_t)((eh + (float)(256 * j)) * inv_kw);
+        lo[j] = __umul24(r, lds_gap) + e;
+        v[j] = (int)e < ne ? src[__umul24(r, src_gap) + e] : 0.f;
     }
+    float *tflat = &tile[0][0];
+#pragma unroll
+    for (int j = 0; j < kTrPerThread; ++j)
+        if ((int)(threadIdx.x + 256u * j) < ne) tflat[lo[j]] = v[j];
     __syncthreads();
-    const int64_t rb = a.rbase[i];
-    const int t = tt * 64 + tx;
-    for (int r = ty; r < 64; r += 4) {
-        const int kk = kt * 64 + r;
-        if (kk < n && t < a.Na) a.xT[(rb + kk) * a.Na + t] = tile[tx][r];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < rows) {
+        float *dst = a.xT + (int64_t)(a.rbase[i] + k0) * a.Na + t0 + lane;
+#pragma unroll 4
+        for (int k = wave; k < kw; k += 4) dst[(int64_t)k * a.Na] = tile[lane][k];
     }
 }
 
 hipError_t launch_an_transpose(const AnChunk &a, int max_n, hipStream_t s)
 {
-    const int ktiles = (max_n + 63) / 64;
+    const int kchunks = (max_n + kTrRegions - 1) / kTrRegions;
     const int ttiles = (a.Na + 63) / 64;
-    dim3 grid((unsigned)(ktiles * ttiles), (unsigned)a.n_inst);
-    hipLaunchKernelGGL(an_transpose_kernel, grid, dim3(256), 0, s, a, ktiles);
+    dim3 grid((unsigned)(kchunks * ttiles), (unsigned)a.n_inst);
+    hipLaunchKernelGGL(an_transpose_kernel, grid, dim3(256), 0, s, a, kchunks);
     return hipGetLastError();
 }
 

@@ -3,8 +3,8 @@
 // 2007 with the classical output coefficients). One thread per region walks
 // the samples in the stored [t][n] layout (the lanes of one instance read
 // consecutive addresses): classical Runge-Kutta with the sample period as the
-// step, the rate (kHz) held over each sample as the neural input, the state in
-// double precision and its derivatives in single precision.
+// step, the rate (kHz) held over each sample as the neural input, the state and
+// its update in double precision, the stage states and derivatives in single.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -15,18 +15,21 @@ namespace vadx {
 namespace {
 
 struct BoldRhs {
-    float kappa, gamma, inv_tau0, inv_alpha, inv_E0, l2_1mE0;   // l2_1mE0 = log2(1 - E0)
+    float kappa, gamma, inv_tau0, inv_alpha_m1, E0tau, l2_1mE0;   // 1/alpha - 1, 1/(E0 tau0), log2(1 - E0)
 };
 
+// The four derivatives of (s, f, v, q) with the neural input z. v^(1/alpha)
+// is taken as v * v^(1/alpha - 1), so that vpow q / v needs no reciprocal.
 __device__ inline void bold_rhs(const BoldRhs &p, float z, float s, float f, float v, float q,
                                 float d[4])
 {
-    const float vpow = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(v) * p.inv_alpha);   // v^(1/alpha)
-    const float ext = 1.f - __builtin_amdgcn_exp2f(p.l2_1mE0 * __builtin_amdgcn_rcpf(f)); // 1 - (1-E0)^(1/f)
+    const float vpow_v = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(v) * p.inv_alpha_m1);   // v^(1/alpha - 1)
+    const float vpow = vpow_v * v;
+    const float ext = 1.f - __builtin_amdgcn_exp2f(p.l2_1mE0 * __builtin_amdgcn_rcpf(f));     // 1 - (1-E0)^(1/f)
     d[0] = z - p.kappa * s - p.gamma * (f - 1.f);
     d[1] = s;
     d[2] = (f - vpow) * p.inv_tau0;
-    d[3] = (f * ext * p.inv_E0 - vpow * q * __builtin_amdgcn_rcpf(v)) * p.inv_tau0;
+    d[3] = f * ext * p.E0tau - vpow_v * q * p.inv_tau0;
 }
 
 } // namespace
@@ -44,30 +47,38 @@ __global__ __launch_bounds__(256) void bold_kernel(BoldArgs a)
     p.kappa = a.kappa;
     p.gamma = a.gamma;
     p.inv_tau0 = a.inv_tau0;
-    p.inv_alpha = a.inv_alpha;
-    p.inv_E0 = a.inv_E0;
+    p.inv_alpha_m1 = a.inv_alpha - 1.f;
+    p.E0tau = a.inv_E0 * a.inv_tau0;
     p.l2_1mE0 = a.l2_1mE0;
-    const double h = a.h, h2 = 0.5 * a.h, h6 = a.h / 6.0;
+    const float hf = (float)a.h, h2f = 0.5f * hf;
+    const double h6 = a.h / 6.0;
+    // The state in double; each step's stage states are formed in single
+    // precision from the state rounded once, as the derivatives take them.
     double X[4] = {0.0, 1.0, 1.0, 1.0};
     int m = 0;
     int next = a.n_tr > 0 ? a.emit[0] : -1;
+    // each sample is loaded one step before it is used (the last load repeats
+    // the last sample, staying in bounds)
+    float znext = a.n_samples > 0 ? *x : 0.f;
     for (int64_t t = 0; t < a.n_samples; ++t) {
-        const float z = x[t * n];
-        float k1[4], k2[4], k3[4], k4[4];
-        double Y[4];
-        bold_rhs(p, z, (float)X[0], (float)X[1], (float)X[2], (float)X[3], k1);
+        const float z = znext;
+        x += t + 1 < a.n_samples ? n : 0;
+        znext = *x;
+        float Xf[4], k1[4], k2[4], k3[4], k4[4], Y[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Y[c] = X[c] + h2 * (double)k1[c];
-        bold_rhs(p, z, (float)Y[0], (float)Y[1], (float)Y[2], (float)Y[3], k2);
+        for (int c = 0; c < 4; ++c) Xf[c] = (float)X[c];
+        bold_rhs(p, z, Xf[0], Xf[1], Xf[2], Xf[3], k1);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Y[c] = X[c] + h2 * (double)k2[c];
-        bold_rhs(p, z, (float)Y[0], (float)Y[1], (float)Y[2], (float)Y[3], k3);
+        for (int c = 0; c < 4; ++c) Y[c] = Xf[c] + h2f * k1[c];
+        bold_rhs(p, z, Y[0], Y[1], Y[2], Y[3], k2);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Y[c] = X[c] + h * (double)k3[c];
-        bold_rhs(p, z, (float)Y[0], (float)Y[1], (float)Y[2], (float)Y[3], k4);
+        for (int c = 0; c < 4; ++c) Y[c] = Xf[c] + h2f * k2[c];
+        bold_rhs(p, z, Y[0], Y[1], Y[2], Y[3], k3);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            X[c] += h6 * ((double)k1[c] + 2.0 * (double)k2[c] + 2.0 * (double)k3[c] + (double)k4[c]);
+        for (int c = 0; c < 4; ++c) Y[c] = Xf[c] + hf * k3[c];
+        bold_rhs(p, z, Y[0], Y[1], Y[2], Y[3], k4);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) X[c] += h6 * (double)((k1[c] + k4[c]) + 2.f * (k2[c] + k3[c]));
         while (next >= 0 && t + 1 >= next) {
             const double y = a.V0 * (a.k1 * (1.0 - X[3]) + a.k2 * (1.0 - X[3] / X[2]) +
                                      a.k3 * (1.0 - X[2]));
