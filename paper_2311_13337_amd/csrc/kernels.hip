@@ -621,6 +621,7 @@ int persistent_blocks_per_cu(int max_block, int block_threads, int occ)
 constexpr int kFcThreads = 256;
 constexpr int kFcStageDoubles = 4096;    // shifted samples staged per chunk (32 KB)
 constexpr int kFcRegionsPerThread = 4;   // regions per thread in the moment sums (n <= 1024)
+constexpr int kFcStagePerThread = kFcStageDoubles / kFcThreads;   // staged samples per thread
 
 // Dynamic LDS of fc_stats_kernel for instances of up to max_n regions: the
 // staged samples, shift / mean / variance per region, a reduction buffer.
@@ -643,7 +644,7 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return r;
 }
 
-__global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
+__global__ __launch_bounds__(kFcThreads, 4) void fc_stats_kernel(FcArgs a)
 {
     extern __shared__ __align__(16) double fcl[];   // fc_lds_bytes(a.max_n)
     double *xs = fcl;                                // [chunk][npad] shifted samples
@@ -667,6 +668,10 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
     const int nT = (n + 3) / 4, npad = nT * 4;
     const int ntiles = nT * (nT + 1) / 2;
     const int chunk = kFcStageDoubles / npad;
+    // e / npad for e < kFcStageDoubles as (e + 1/2) times the rounded
+    // reciprocal, truncated: the quotient stays at least 1/(2 npad) from an
+    // integer, its rounding error below e 2^-23 / npad, so the row is exact
+    const float inv_npad = 1.f / (float)npad;
     double s_f = 0, s_f2 = 0, s_w = 0, s_w2 = 0, s_fw = 0, s_cov = 0;
     double s_r = 0, s_r2 = 0, s_fr = 0;           // reference FC (fitness)
     // per-region sums of the shifted samples and of their squares, gathered
@@ -689,10 +694,30 @@ __global__ __launch_bounds__(kFcThreads) void fc_stats_kernel(FcArgs a)
             for (int j = 0; j < 4; ++j) P[i][j] = 0.0;
         for (int64_t s0 = 0; s0 < ns; s0 += chunk) {
             const int cn = (int)((ns - s0) < chunk ? (ns - s0) : chunk);
+            // stage the chunk: element e = s npad + k (sample s, region k) of
+            // the LDS block comes from x[(s0 + s) n + k]; a thread issues all
+            // its loads before storing any
+            const int ne = cn * npad;
+            const float *xc = x + s0 * n;
+            float v[kFcStagePerThread];
+#pragma unroll
+            for (int j = 0; j < kFcStagePerThread; ++j) {
+                const int e = tid + j * kFcThreads;
+                const int sj = (int)(((float)e + 0.5f) * inv_npad), kj = e - sj * npad;
+                // unconditional loads (elements outside the chunk or in the
+                // padding read the chunk's first sample, unused)
+                v[j] = xc[(e < ne && kj < n) ? sj * n + kj : 0];
+            }
             __syncthreads();
-            for (int i = tid; i < cn * npad; i += kFcThreads) {
-                const int s = i / npad, k = i - s * npad;
-                xs[i] = k < n ? (double)x[(s0 + s) * n + k] - shift[k] : 0.0;
+            // the stores re-derive the indices from an opaque copy of tid, so
+            // that only the loaded values stay live between the two loops
+            int tid2 = tid;
+            asm volatile("" : "+v"(tid2));
+#pragma unroll
+            for (int j = 0; j < kFcStagePerThread; ++j) {
+                const int e = tid2 + j * kFcThreads;
+                const int sj = (int)(((float)e + 0.5f) * inv_npad), kj = e - sj * npad;
+                if (e < ne) xs[e] = kj < n ? (double)v[j] - shift[kj] : 0.0;
             }
             __syncthreads();
             if (t0 == 0) {
