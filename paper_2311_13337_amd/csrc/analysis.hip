@@ -252,15 +252,15 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
         for (int e = tid; e < (np << a.log2L); e += kWelchThreads) {
             const int p = p0 + (e >> a.log2L), m = e & (L - 1);
             const int sa = 2 * p, sb = sa + 1;
+            // an odd last segment rides alone: its partner's loads repeat
+            // segment sa (unconditional loads stay in flight together) and
+            // the imaginary part is zero
+            const int sbl = sb < a.n_seg ? sb : sa;
             const float w = a.hann[m];
-            const float *xa = x + sa * hop;
+            const float *xa = x + sa * hop, *xb = x + sbl * hop;
             const float re = ((xa[m] - xa[0]) - smean[sa]) * w;
-            float im = 0.f;
-            if (sb < a.n_seg) {
-                const float *xb = x + sb * hop;
-                im = ((xb[m] - xb[0]) - smean[sb]) * w;
-            }
-            buf[e] = make_float2(re, im);
+            const float im = ((xb[m] - xb[0]) - smean[sbl]) * w;
+            buf[e] = make_float2(re, sb < a.n_seg ? im : 0.f);
         }
         __syncthreads();
         fft_lds<kWelchThreads, kWelchBatch / 4 / kWelchThreads, false>(buf, a.log2L, np, tw);
@@ -305,6 +305,8 @@ hipError_t launch_an_welch(const AnChunk &a, hipStream_t s)
 // W = exp(-2 pi i / N). The analytic weights are applied on the way (bin 0 to
 // zero, bins 1..M-1 doubled, bin M kept, bins above M zero), then the inverse
 // transform of length N, scaled by 1/N.
+constexpr int kHilbertStageBatch = 8;   // window loads in flight per thread
+
 template <int Q4>
 __global__ __launch_bounds__(kHilbertThreads) void an_hilbert_kernel(AnChunk a)
 {
@@ -317,7 +319,19 @@ __global__ __launch_bounds__(kHilbertThreads) void an_hilbert_kernel(AnChunk a)
     const int N = a.Na, M = N >> 1;
     const float *x = a.xT + g * N;
     load_twiddles(tw, a.tw);
-    for (int m = tid; m < M; m += NT) buf[m] = make_float2(x[2 * m], x[2 * m + 1]);
+    // kHilbertStageBatch loads in flight per thread before their LDS stores
+    // (indices past the window load its first pair, unused)
+    for (int m0 = tid; m0 < M; m0 += kHilbertStageBatch * NT) {
+        float2 v[kHilbertStageBatch];
+#pragma unroll
+        for (int j = 0; j < kHilbertStageBatch; ++j) {
+            const int m = m0 + j * NT, mm = m < M ? m : 0;
+            v[j] = make_float2(x[2 * mm], x[2 * mm + 1]);
+        }
+#pragma unroll
+        for (int j = 0; j < kHilbertStageBatch; ++j)
+            if (m0 + j * NT < M) buf[m0 + j * NT] = v[j];
+    }
     __syncthreads();
     fft_lds<NT, Q4, false>(buf, a.log2Na - 1, 1, tw);
     float2 ca[PM], cb[PM];
@@ -406,6 +420,8 @@ int pli_passes(int n)
     return (tiles + kPliThreads - 1) / kPliThreads;
 }
 
+constexpr int kPliStageBatch = 8;   // staging loads in flight per thread
+
 __global__ __launch_bounds__(kPliThreads) void an_pli_kernel(AnChunk a)
 {
     extern __shared__ float2 zs[];                // [n][tc + 1]
@@ -437,10 +453,23 @@ __global__ __launch_bounds__(kPliThreads) void an_pli_kernel(AnChunk a)
         kr[p] = min(k0 + p, n - 1) * ld;
         lr[p] = min(l0 + p, n - 1) * ld;
     }
+    // tc is a power of two: element e of a chunk is region e >> ltc, sample
+    // e & (tc - 1); a thread issues kPliStageBatch loads before storing them
+    // (elements past the chunk load its first one, unused)
+    const int ltc = __builtin_ctz((unsigned)tc), ne = n * tc;
     for (int t0 = 0; t0 < a.Na; t0 += tc) {
-        for (int e = tid; e < n * tc; e += kPliThreads) {
-            const int k = e / tc, tt = e - k * tc;
-            zs[k * ld + tt] = z[(int64_t)k * a.Na + t0 + tt];
+        for (int e0 = tid; e0 < ne; e0 += kPliStageBatch * kPliThreads) {
+            float2 v[kPliStageBatch];
+#pragma unroll
+            for (int j = 0; j < kPliStageBatch; ++j) {
+                const int e = e0 + j * kPliThreads, ee = e < ne ? e : 0;
+                v[j] = z[(int64_t)(ee >> ltc) * a.Na + t0 + (ee & (tc - 1))];
+            }
+#pragma unroll
+            for (int j = 0; j < kPliStageBatch; ++j) {
+                const int e = e0 + j * kPliThreads;
+                if (e < ne) zs[(e >> ltc) * ld + (e & (tc - 1))] = v[j];
+            }
         }
         __syncthreads();
         if (active) {
