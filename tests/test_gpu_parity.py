@@ -531,6 +531,23 @@ def test_largest_region_count(oracle):
         check_trace(g, ref["trace"][i], pert["trace"][i], f"512-region instance {i}")
 
 
+@pytest.mark.parametrize("n", [5, 37, 130, 509])
+def test_fc_on_own_samples_padded_region_counts(oracle, n):
+    """The FC kernel on region counts that are not multiples of its 4 x 4
+    tiles (the staged rows carry 1-3 padding columns): 5 regions (one
+    512-sample chunk), 37 (chunks of 102 samples), 130 (31) and 509 (8, and
+    33 passes of 256 tiles), 250 samples each, so every size ends on a ragged
+    chunk; against the oracle's FC of the GPU's own samples."""
+    conn = inputs.synthetic_connectome(n, seed=n)
+    rng = np.random.default_rng(n)
+    batch = inputs._batch(rng.uniform(0.05, 0.3, 3), rng.uniform(0, 60, 3), rng.uniform(0, 4, 3),
+                          rng.uniform(3.0, 6.0, 3))
+    cfg = inputs.RunConfig(n_steps=3000, transient_steps=500, seed=n)
+    print(f"[parity] FC of {n}-region instances on their own samples", flush=True)
+    sw = run_gpu("literature-B", [conn], batch, cfg)
+    assert check_fc_samples(oracle, sw, range(3), lambda i: conn, f"{n} regions") == 3
+
+
 @pytest.mark.parametrize("integrator,noise_off", [(1, False), (0, True)])
 def test_euler_and_noise_free(oracle, integrator, noise_off):
     conn = inputs.synthetic_connectome(68)
