@@ -144,6 +144,20 @@ __device__ inline float wave_sum(float v)
     return v;
 }
 
+__device__ inline float wave_min(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+__device__ inline float wave_max(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
 } // namespace
 
 // ------------------------------------------------------------------ transpose
@@ -223,6 +237,7 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
 {
     extern __shared__ float2 buf[];               // kWelchBatch complex values
     __shared__ float smean[kMaxSegments];         // mean deviation from the segment's first sample
+    __shared__ float smm[2][kWelchThreads / 64];  // per-wave min and max of the window
     __shared__ TwLds tw;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t g = blockIdx.x;
@@ -230,16 +245,40 @@ __global__ __launch_bounds__(kWelchThreads) void an_welch_kernel(AnChunk a)
     const int L = a.L, hop = L >> 1;
     const float invL = 1.f / (float)L;            // a power of two: exact
     load_twiddles(tw, a.tw);
+    // the segments (hop L/2, (Na - L)/hop + 1 of them) cover the window
+    // exactly, so the same pass takes the window's min and max for the
+    // Up/Down kernel
+    float wmn = INFINITY, wmx = -INFINITY;
     for (int sg = wave; sg < a.n_seg; sg += kWelchThreads / 64) {
         const float *xs = x + sg * hop;
         const float ref = xs[0];
         float s = 0.f;
 #pragma unroll 4
-        for (int m = lane; m < L; m += 64) s += xs[m] - ref;
+        for (int m = lane; m < L; m += 64) {
+            const float v = xs[m];
+            s += v - ref;
+            wmn = fminf(wmn, v);
+            wmx = fmaxf(wmx, v);
+        }
         s = wave_sum(s);
         if (lane == 0) smean[sg] = s * invL;
     }
+    wmn = wave_min(wmn);
+    wmx = wave_max(wmx);
+    if (lane == 0) {
+        smm[0][wave] = wmn;
+        smm[1][wave] = wmx;
+    }
     __syncthreads();
+    if (tid == 0) {
+        float mn = smm[0][0], mx = smm[1][0];
+        for (int w = 1; w < kWelchThreads / 64; ++w) {
+            mn = fminf(mn, smm[0][w]);
+            mx = fmaxf(mx, smm[1][w]);
+        }
+        a.ud[g * 4] = __float_as_int(mn);
+        a.ud[g * 4 + 1] = __float_as_int(mx);
+    }
     const int nb2 = L / 2 + 1;
     float acc[kWelchBinsPerThread];
 #pragma unroll
@@ -536,9 +575,10 @@ hipError_t launch_an_pli(const AnChunk &a, int max_n, hipStream_t s)
 
 // --------------------------------------------------------------------- Up/Down
 // One thread per region, reading the window in the stored [t][n] layout (lanes
-// of one instance read consecutive addresses). Thresholds are formed in single
-// precision without contraction, so they equal those of any other
-// single-precision evaluation of the same expressions.
+// of one instance read consecutive addresses) once: its min and max come from
+// the Welch kernel. Thresholds are formed in single precision without
+// contraction, so they equal those of any other single-precision evaluation of
+// the same expressions.
 constexpr int kUdUnroll = 16;
 
 __global__ __launch_bounds__(kUdThreads) void an_ud_kernel(AnChunk a)
@@ -550,19 +590,11 @@ __global__ __launch_bounds__(kUdThreads) void an_ud_kernel(AnChunk a)
     const int n = a.n[i];
     const int k = g - a.rbase[i];
     const float *x = a.samples + a.samp_off[i] + (a.n_samples - a.Na) * (int64_t)n + k;
-    // both passes load kUdUnroll samples before using any (more loads in flight
-    // per thread; the window length is a power of two >= 16)
-    float mn = x[0], mx = x[0];
-    for (int t0 = 0; t0 < a.Na; t0 += kUdUnroll) {
-        float v[kUdUnroll];
-#pragma unroll
-        for (int u = 0; u < kUdUnroll; ++u) v[u] = x[(int64_t)(t0 + u) * n];
-#pragma unroll
-        for (int u = 0; u < kUdUnroll; ++u) {
-            mn = fminf(mn, v[u]);
-            mx = fmaxf(mx, v[u]);
-        }
-    }
+    // the window's min and max, left in this region's slots by the Welch
+    // kernel; the pass loads kUdUnroll samples before using any (more loads in
+    // flight per thread; the window length is a power of two >= 16)
+    int32_t *o = a.ud + (int64_t)g * 4;
+    const float mn = __int_as_float(o[0]), mx = __int_as_float(o[1]);
     int su = 0, nu = 0, sd = 0, nd = 0;
     const float r = mx - mn;
     if (r >= a.ud_min_range) {
@@ -593,7 +625,6 @@ __global__ __launch_bounds__(kUdThreads) void an_ud_kernel(AnChunk a)
             }
         }
     }
-    int32_t *o = a.ud + (int64_t)g * 4;
     o[0] = su;
     o[1] = nu;
     o[2] = sd;

@@ -51,7 +51,8 @@ struct AnChunk {
     float *xT;                   // [R][Na] window, time-contiguous
     float2 *z;                   // [R][Na] analytic signals
     float *psd;                  // [R][L/2+1]
-    int32_t *ud;                 // [R][4] Up sum, Up count, Down sum, Down count
+    int32_t *ud;                 // [R][4] Up sum, Up count, Down sum, Down count (slots 0, 1 carry
+                                 // the window's min, max as float bits from Welch to Up/Down)
     float *pli_part;             // [I][pli_passes] sums of PLI over a workgroup's pairs
     float *pli_out;              // nullable
     vadx_analysis *out;          // [I] results of this chunk's instances
