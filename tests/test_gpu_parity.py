@@ -111,7 +111,7 @@ def oracle_ensemble(oracle, preset, conn, batch, cfg, inst_ids=None):
                        want_samples=False) for r in ENSEMBLE]
 
 
-def fc_verdict(label, fc, st, ens, q):
+def fc_outcome(label, fc, st, ens, q):
     """(ok, message) of one GPU FC/statistics against the oracle ensemble."""
     ref = ens[0]["fc"][q]
     spread = max(np.abs(e["fc"][q] - ref).max() for e in ens[1:])
@@ -173,7 +173,7 @@ def check_fc(label, fc, st, ens, q, paths=None):
     print(f"[parity] {label}: max|dFC| {d.max():.3g} mean {d.mean():.3g}; ensemble max "
           f"{spread:.3g}; fc_mean gpu {gst[0]:.4f} oracle {ost[:, 0].min():.4f}.."
           f"{ost[:, 0].max():.4f}", flush=True)
-    ok, msg = fc_verdict(label, fc, st, ens, q)
+    ok, msg = fc_outcome(label, fc, st, ens, q)
     if not ok and paths is not None and spread >= 1e-3 and (st["flags"] & 1) == 0:
         ok = within_path_distribution(st, paths)
         print(f"[parity] {label}: same-path criteria not met ({msg}); within the oracle's "
