@@ -63,6 +63,9 @@ __device__ __forceinline__ f32x4 mfma_tile(const uint16_t *a, int a_rs, int a_cs
 constexpr int T = kMlpTile;   // samples per workgroup
 constexpr int H = 128;
 
+constexpr int kStageBatch = 16;   // W2 loads in flight per thread (H * H = 4 batches of 256 x 16)
+static_assert((H * H) % (kStageBatch * 256) == 0, "W2 staging covers whole batches");
+
 __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a, const float *__restrict__ X,
                                                        const float *__restrict__ Y, int n,
                                                        float inv_n6)
@@ -77,7 +80,15 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a, const float *_
     const float *W1 = a.params, *b1 = W1 + H * 4, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H,
                 *b3 = W3 + 6 * H;
     float *g = a.partial + (int64_t)blockIdx.x * kMlpSlot;
-    for (int i = tid; i < H * H; i += 256) W2b[i] = to_bf16(W2[i]);
+    // W2 to bfloat16 in LDS, kStageBatch loads in flight per thread before
+    // their conversions (one at a time, the staging was most of a launch)
+    for (int i0 = tid; i0 < H * H; i0 += kStageBatch * 256) {
+        float v[kStageBatch];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) v[j] = W2[i0 + j * 256];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) W2b[i0 + j * 256] = to_bf16(v[j]);
+    }
     for (int i = tid; i < H * 4; i += 256) W1s[i] = rbf(W1[i]);
     for (int i = tid; i < 6 * H; i += 256) W3s[i] = rbf(W3[i]);
     for (int i = tid; i < T * 4; i += 256) {
@@ -202,15 +213,33 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a, const float *_
     }
 }
 
+// Sums slot entry e of the n_tiles tile slots in tile order, kSumBatch loads
+// in flight at a time.
+constexpr int kSumBatch = 8;
+__device__ inline float tile_sum(const float *partial, int n_tiles, int e)
+{
+    float gs = 0.f;
+    int t = 0;
+    for (; t + kSumBatch <= n_tiles; t += kSumBatch) {
+        float v[kSumBatch];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) v[u] = partial[(int64_t)(t + u) * kMlpSlot + e];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) gs += v[u];
+    }
+    for (; t < n_tiles; ++t) gs += partial[(int64_t)t * kMlpSlot + e];
+    return gs;
+}
+
 // Sums the tile gradients in tile order (deterministic) and applies Adam.
 // c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t). apply = 0 only sums (gradient
-// read-out); the loss sum goes to a.loss_out[step].
+// read-out); the loss sum goes to a.loss_out[step], taken by the thread past
+// the last parameter (the grid holds one) alongside the parameters' sums.
 __global__ void mlp_adam_kernel(MlpArgs a, int n_tiles, float c1, float c2, int apply, int step)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < kMlpParams) {
-        float gs = 0.f;
-        for (int t = 0; t < n_tiles; ++t) gs += a.partial[(int64_t)t * kMlpSlot + p];
+        const float gs = tile_sum(a.partial, n_tiles, p);
         a.grad[p] = gs;
         if (apply) {
             const float m = a.beta1 * a.m[p] + (1.f - a.beta1) * gs;
@@ -220,11 +249,7 @@ __global__ void mlp_adam_kernel(MlpArgs a, int n_tiles, float c1, float c2, int 
             a.params[p] -= a.lr * (m * c1) / (sqrtf(v * c2) + a.eps);
         }
     }
-    if (p == 0 && a.loss_out) {
-        float l = 0.f;
-        for (int t = 0; t < n_tiles; ++t) l += a.partial[(int64_t)t * kMlpSlot + kMlpOffLoss];
-        a.loss_out[step] = l;
-    }
+    if (p == kMlpParams && a.loss_out) a.loss_out[step] = tile_sum(a.partial, n_tiles, kMlpOffLoss);
 }
 
 // Forward pass for tiles of 32 points; Jacobian by forward-mode tangents:
@@ -339,7 +364,7 @@ hipError_t launch_mlp_grad(const MlpArgs &a, const float *X, const float *Y, int
 hipError_t launch_mlp_adam(const MlpArgs &a, int n_tiles, float c1, float c2, int apply, int step,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, a,
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, a,
                        n_tiles, c1, c2, apply, step);
     return hipGetLastError();
 }
