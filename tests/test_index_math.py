@@ -48,3 +48,23 @@ def test_transpose_walk_covers_tile_once(kw):
                     seen[r, e - r * kw] += 1
         assert (seen[:rows, :kw] == 1).all()
         assert seen.sum() == ne
+
+
+def test_welch_segments_cover_the_window():
+    """The Up/Down kernel takes each region's min and max from the Welch
+    kernel's segment pass, so the segments (length L, hop L/2, (Na - L)/hop + 1
+    of them, as the host computes them) must cover the window [0, Na) exactly
+    for every window and segment length the analysis accepts (powers of two,
+    16 <= L <= min(Na, 8192), Na <= 16384)."""
+    for lna in range(4, 15):
+        Na = 1 << lna
+        for lL in range(4, 14):
+            L = 1 << lL
+            if L > Na:
+                continue
+            hop = L // 2
+            n_seg = (Na - L) // hop + 1
+            covered = np.zeros(Na, bool)
+            for sg in range(n_seg):
+                covered[sg * hop:sg * hop + L] = True
+            assert covered.all() and (n_seg - 1) * hop + L == Na, (Na, L)
