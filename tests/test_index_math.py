@@ -4,7 +4,8 @@ element e as (e + 1/2) times the single-precision reciprocal of the row length,
 truncated, instead of an integer division; this is exact only over the ranges
 the kernels use, which these tests cover exhaustively in IEEE single precision
 (the same operations the device code performs: a correctly rounded 1/w, an
-exact e + 1/2, one rounded product)."""
+exact e + 1/2, one rounded product). Also the coverage of the analysis window
+by the Welch segments, on which the Up/Down kernel's min and max rely."""
 import numpy as np
 import pytest
 
