@@ -66,6 +66,20 @@ constexpr int H = 128;
 constexpr int kStageBatch = 16;   // W2 loads in flight per thread (H * H = 4 batches of 256 x 16)
 static_assert((H * H) % (kStageBatch * 256) == 0, "W2 staging covers whole batches");
 
+// W2 to bfloat16 in LDS by a 256-thread workgroup, kStageBatch loads in flight
+// per thread before their conversions (one load and wait at a time, the staging
+// was most of a gradient launch).
+__device__ inline void stage_w2(uint16_t *W2b, const float *W2, int tid)
+{
+    for (int i0 = tid; i0 < H * H; i0 += kStageBatch * 256) {
+        float v[kStageBatch];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) v[j] = W2[i0 + j * 256];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) W2b[i0 + j * 256] = to_bf16(v[j]);
+    }
+}
+
 __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a, const float *__restrict__ X,
                                                        const float *__restrict__ Y, int n,
                                                        float inv_n6)
@@ -80,15 +94,7 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a, const float *_
     const float *W1 = a.params, *b1 = W1 + H * 4, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H,
                 *b3 = W3 + 6 * H;
     float *g = a.partial + (int64_t)blockIdx.x * kMlpSlot;
-    // W2 to bfloat16 in LDS, kStageBatch loads in flight per thread before
-    // their conversions (one at a time, the staging was most of a launch)
-    for (int i0 = tid; i0 < H * H; i0 += kStageBatch * 256) {
-        float v[kStageBatch];
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j) v[j] = W2[i0 + j * 256];
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j) W2b[i0 + j * 256] = to_bf16(v[j]);
-    }
+    stage_w2(W2b, W2, tid);
     for (int i = tid; i < H * 4; i += 256) W1s[i] = rbf(W1[i]);
     for (int i = tid; i < 6 * H; i += 256) W3s[i] = rbf(W3[i]);
     for (int i = tid; i < T * 4; i += 256) {
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(256) void mlp_predict_kernel(MlpArgs a, const float
     const bool jac = Jout != nullptr || score != nullptr;
     const float *W1 = a.params, *b1 = W1 + H * 4, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H,
                 *b3 = W3 + 6 * H;
-    for (int i = tid; i < H * H; i += 256) W2b[i] = to_bf16(W2[i]);
+    stage_w2(W2b, W2, tid);
     for (int i = tid; i < H * 4; i += 256) W1s[i] = rbf(W1[i]);
     for (int i = tid; i < 6 * H; i += 256) W3s[i] = rbf(W3[i]);
     for (int i = tid; i < T * 4 * 6; i += 256) Jacc[i] = 0.f;
